@@ -1,0 +1,345 @@
+"""Pins of the FP64 oracle to facts outside itself (CPU only).
+
+Every pin is a function returning (ok, detail) so that the mutation test at
+the end can run them all with a deliberate mistake planted in the oracle and
+check that each mistake is caught by at least one pin.
+"""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import nnls
+
+import cbct_synth as S
+import oracle as O
+from tests import brute
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+G1 = S.config_geometry("cfg1")
+# tiny anisotropic grid, off-centre-sized detector, 3 views at irregular angles
+TINY = dataclasses.replace(G1, nx=5, ny=4, nz=3, hx=2.0, hy=1.5, hz=2.5, nu=6, nv=4, pu=3.0, pv=4.0,
+                           n_views=3, angles=(0.3, 2.1, 4.4))
+SMALL = dataclasses.replace(G1, nx=16, ny=12, nz=10, nu=20, nv=14, n_views=5)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+# ------------------------------------------------------------------ operator pins
+def pin_brute_forward():
+    """Oracle P = dense brute-force A x on a tiny anisotropic problem (1e-12)."""
+    x = S.random_volume(TINY, 3, "normal")
+    e = _rel(O.forward(TINY, x), brute.forward(TINY, x))
+    return e < 1e-12, e
+
+
+def pin_brute_adjoint():
+    """Oracle P^T = A^T y with A the brute-force dense matrix (1e-12)."""
+    A = brute.matrix(TINY)
+    y = S.random_projections(TINY, 4, "normal")
+    e = _rel(O.adjoint(TINY, y).ravel(), A.T @ y.ravel())
+    return e < 1e-12, e
+
+
+def pin_adjoint_identity():
+    """<Px, y> = <x, P^T y> on random vectors (1e-12)."""
+    worst = 0.0
+    for g, seed in ((SMALL, 5), (G1, 6)):
+        x = S.random_volume(g, seed, "normal")
+        y = S.random_projections(g, seed + 100, "normal")
+        a, b = np.vdot(O.forward(g, x), y), np.vdot(x, O.adjoint(g, y))
+        worst = max(worst, abs(a - b) / abs(a))
+    return worst < 1e-12, worst
+
+
+_ELL = S.Ellipsoid((6.0, -4.0, 3.0), (22.0, 12.0, 15.0), 0.7, 0.01)
+_BALL = S.Ellipsoid((5.0, -7.0, 4.0), (18.0, 18.0, 18.0), 0.0, 0.01)
+_G1_FINE = dataclasses.replace(G1, nx=64, ny=64, nz=64, hx=1.0, hy=1.0, hz=1.0, nu=128, nv=128, pu=0.75, pv=0.75)
+
+
+def _chord_err(g, body):
+    f0 = S.voxelize(g, [body], 4)
+    return _rel(O.forward(g, f0), S.analytic_projections(g, [body]))
+
+
+def pin_chords():
+    """P of a voxelised ball and of a rotated off-centre ellipsoid against their exact
+    chords: rel-L2 <= 6 % at the 2 mm grid, and at least 1.6x smaller on a 2x finer grid."""
+    out = {}
+    ok = True
+    for name, body in (("ball", _BALL), ("ellipsoid", _ELL)):
+        e1, e2 = _chord_err(G1, body), _chord_err(_G1_FINE, body)
+        out[name] = (e1, e2)
+        ok &= (e1 < 0.06) and (e2 < e1 / 1.6)
+    return ok, out
+
+
+def pin_mass():
+    """Detector-integrated projection per view equals the exact one (0.3 %):
+    scale of P including the 3-D step weight."""
+    f0 = S.voxelize(G1, [_ELL], 4)
+    m1 = O.forward(G1, f0).sum(axis=(1, 2))
+    m2 = S.analytic_projections(G1, [_ELL]).sum(axis=(1, 2))
+    e = float(np.max(np.abs(m1 - m2) / m2))
+    return e < 3e-3, e
+
+
+def pin_box():
+    """P 1 against the chord through the grid box (voxel centres +- h/2): 2 % at the 2 mm
+    grid, smaller on the finer grid."""
+    errs = []
+    for g in (G1, _G1_FINE):
+        half = np.array([g.nx * g.hx, g.ny * g.hy, g.nz * g.hz]) / 2
+        errs.append(_rel(O.forward(g, np.ones(g.vol_shape)), brute.box_chords(g, half)))
+    return errs[0] < 0.02 and errs[1] < errs[0], errs
+
+
+def pin_centroid():
+    """A small off-centre ball projects to (u*, v*) of Eq. (A6) at theta = 0 and 90 deg
+    (within 1/20 pixel)."""
+    g = dataclasses.replace(G1, nu=256, nv=256, pu=0.375, pv=0.375, n_views=2, angles=(0.0, np.pi / 2))
+    c = np.array([15.0, -10.0, 8.0])
+    f0 = S.voxelize(g, [S.Ellipsoid(tuple(c), (3.0, 3.0, 3.0), 0.0, 0.01)], 4)
+    Pf = O.forward(g, f0)
+    u = (np.arange(g.nu) - (g.nu - 1) / 2) * g.pu
+    v = (np.arange(g.nv) - (g.nv - 1) / 2) * g.pv
+    worst = 0.0
+    for k, th in enumerate(g.angles):
+        img = Pf[k]
+        uc = (img.sum(0) * u).sum() / img.sum()
+        vc = (img.sum(1) * v).sum() / img.sum()
+        us, vs, _, _ = brute.appendix_uv(g, th, c)
+        worst = max(worst, abs(uc - us) / g.pu, abs(vc - vs) / g.pv)
+    return worst < 0.05, worst
+
+
+def pin_continuum_adjoint():
+    """P^T y of a smooth y against the closed-form gradient of Eq. (6) / Jacobian (A7):
+    (hx hy hz / (pu pv)) sum_theta L^3/(L0 l^2) y(u*, v*) at interior voxels (3 % max, 0.6 % rms)."""
+    g = dataclasses.replace(G1, nu=128, nv=128, pu=0.75, pv=0.75, n_views=4)
+    u = (np.arange(g.nu) - (g.nu - 1) / 2) * g.pu
+    v = (np.arange(g.nv) - (g.nv - 1) / 2) * g.pv
+
+    def yfun(uu, vv):
+        return 1 + 0.5 * np.cos(2 * np.pi * uu / 70.0) * np.cos(2 * np.pi * vv / 55.0 + 0.3)
+
+    Y = np.broadcast_to(yfun(u[None, :], v[:, None]), g.proj_shape).copy()
+    Pt = O.adjoint(g, Y)
+    xs = (np.arange(g.nx) - (g.nx - 1) / 2) * g.hx
+    ys = (np.arange(g.ny) - (g.ny - 1) / 2) * g.hy
+    zs = (np.arange(g.nz) - (g.nz - 1) / 2) * g.hz
+    Z, Yy, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    expect = np.zeros(g.vol_shape)
+    for k in range(g.n_views):
+        us, vs, ls, L = brute.appendix_uv(g, 2 * np.pi * k / g.n_views, (X, Yy, Z))
+        expect += L ** 3 / (g.sdd * ls ** 2) * yfun(us, vs)
+    expect *= g.hx * g.hy * g.hz / (g.pu * g.pv)
+    sl = (slice(4, -4),) * 3
+    err = np.abs(Pt[sl] - expect[sl]) / expect[sl]
+    mx, rms = float(err.max()), float(np.sqrt((err ** 2).mean()))
+    return mx < 0.03 and rms < 0.006, (mx, rms)
+
+
+# ------------------------------------------------------------------ TV pins
+TVG = dataclasses.replace(G1, nx=6, ny=5, nz=4, hx=1.0, hy=1.5, hz=2.5)
+
+
+def pin_tv_gradient():
+    """dR/df against FP64 central differences of R on a random volume (1e-7 rel)."""
+    f = S.random_volume(TVG, 7) * 0.02
+    grad = O.tv_grad(TVG, f, 1e-5)
+    h = 1e-7
+    num = np.zeros_like(f)
+    for q in range(f.size):
+        fp = f.copy(); fp.flat[q] += h
+        fm = f.copy(); fm.flat[q] -= h
+        num.flat[q] = (O.tv_energy(TVG, fp, 1e-5) - O.tv_energy(TVG, fm, 1e-5)) / (2 * h)
+    e = _rel(grad, num)
+    return e < 1e-6, e
+
+
+def pin_tv_closed_forms():
+    """R of special volumes in closed form: a constant volume (only the upper x and y faces
+    jump, z is reflective) and a linear ramp along z (zero BC in x, y; reflective in z)."""
+    g = TVG
+    eps = 1e-5
+    n = g.nx * g.ny * g.nz
+    # constant 1: Dx = -1/hx on the last x column, Dy = -1/hy on the last y row, Dz = 0
+    cnt_x = g.ny * g.nz - g.nz  # last-x but not last-y
+    cnt_y = g.nx * g.nz - g.nz
+    cnt_xy = g.nz
+    cnt_0 = n - cnt_x - cnt_y - cnt_xy
+    R1 = (cnt_0 * eps + cnt_x * np.hypot(1 / g.hx, eps) + cnt_y * np.hypot(1 / g.hy, eps)
+          + cnt_xy * np.sqrt(1 / g.hx ** 2 + 1 / g.hy ** 2 + eps ** 2)) / n
+    # ramp f = s*c along z: Dz = s/hz except at the last plane (0); x/y faces jump by -f
+    s = 0.01
+    f = np.broadcast_to((s * np.arange(g.nz))[:, None, None], g.vol_shape).copy()
+    tot = 0.0
+    for c in range(g.nz):
+        dz = s / g.hz if c + 1 < g.nz else 0.0
+        val = s * c
+        for b in range(g.ny):
+            for a in range(g.nx):
+                dx = -val / g.hx if a == g.nx - 1 else 0.0
+                dy = -val / g.hy if b == g.ny - 1 else 0.0
+                tot += np.sqrt(dx * dx + dy * dy + dz * dz + eps * eps)
+    R2 = tot / n
+    e1 = abs(O.tv_energy(g, np.ones(g.vol_shape), eps) - R1) / R1
+    e2 = abs(O.tv_energy(g, f, eps) - R2) / R2
+    return max(e1, e2) < 1e-12, (e1, e2)
+
+
+# ------------------------------------------------------------------ multigrid pins
+def pin_transfers():
+    """<Prol x, y> = 8 <x, R y>; R 1 = 1; Prol reproduces linear fields away from the clamped
+    edges; Prol 1 = 1."""
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((3, 4, 5))
+    y = rng.standard_normal((6, 8, 10))
+    a, b = np.vdot(O.prolong(x), y), 8 * np.vdot(x, O.restrict(y))
+    e_adj = abs(a - b) / abs(a)
+    e_r1 = float(np.max(np.abs(O.restrict(np.ones((6, 8, 10))) - 1)))
+    e_p1 = float(np.max(np.abs(O.prolong(np.ones((3, 4, 5))) - 1)))
+    # linear field in coarse cell coordinates; fine cell C sits at coarse coordinate (C - 0.5)/2
+    cz, cy, cx = np.meshgrid(np.arange(4), np.arange(5), np.arange(6), indexing="ij")
+    lin = 0.3 * cx - 0.7 * cy + 1.1 * cz + 2.0
+    fz, fy, fx = np.meshgrid((np.arange(8) - 0.5) / 2, (np.arange(10) - 0.5) / 2, (np.arange(12) - 0.5) / 2,
+                             indexing="ij")
+    want = 0.3 * fx - 0.7 * fy + 1.1 * fz + 2.0
+    got = O.prolong(lin)
+    e_lin = float(np.max(np.abs(got[1:-1, 1:-1, 1:-1] - want[1:-1, 1:-1, 1:-1])))
+    ok = e_adj < 1e-12 and e_r1 < 1e-12 and e_p1 < 1e-12 and e_lin < 1e-12
+    return ok, (e_adj, e_r1, e_p1, e_lin)
+
+
+def pin_binning():
+    """Detector binning = block mean."""
+    Y = np.random.default_rng(9).standard_normal((2, 8, 6))
+    want = Y.reshape(2, 4, 2, 3, 2).mean(axis=(2, 4))
+    e = float(np.max(np.abs(O.bin_detector(Y, 2) - want)))
+    return e < 1e-14, e
+
+
+# ------------------------------------------------------------------ solver pins
+def _cfg1_data():
+    ph = S.make_phantom(G1, 11)
+    return S.poisson_log(S.analytic_projections(G1, ph), 1e5, 12)
+
+
+def pin_rof_armijo():
+    """Every ROF step obeys Eq. (5) with c = 0.01, alpha = 0.6: accepted steps satisfy
+    E_new <= E0 - c t alpha^m G (so E_R strictly decreases); a refused search fails the test
+    at m = 30.  Run with a large t so that backtracking occurs."""
+    g = dataclasses.replace(G1, nx=12, ny=12, nz=8)
+    gv = S.random_volume(g, 10) * 0.02
+    t = 2.0
+    res = O.rof(g, gv, 0.05, t)
+    c, alpha = GOLD["armijo"]["c"], GOLD["armijo"]["alpha"]
+    ok, backtracked = True, False
+    for (lvl, outer, inner, m), (e0, enew, G) in zip(res.trace, res.rof_e):
+        if m >= 0:
+            s = t * alpha ** m
+            ok &= bool(enew <= e0 - c * s * G) and bool(enew < e0)
+            backtracked |= m > 0
+        else:
+            ok &= bool(enew > e0 - c * t * alpha ** 30 * G)
+    return ok and backtracked and len(res.trace) > 0, (len(res.trace), res.trace[:, 3].tolist())
+
+
+def pin_fbs_monotone():
+    """E(f_k) = D + lambda R is non-increasing over 20 outer iterations on the 32^3
+    workload (slack 1e-9 E)."""
+    Y = _cfg1_data()
+    res = O.reconstruct(G1, Y, 0.05, [20], 1)
+    e = res.energy
+    viol = float(np.max(np.diff(e) - 1e-9 * e[:-1]))
+    return viol <= 0 and e[-1] < 0.01 * e[0], (viol, e[0], e[-1])
+
+
+def pin_nnls():
+    """lambda = 0 reduces the method to projected gradient descent on D: after many
+    iterations its objective matches scipy's NNLS on the dense brute-force matrix (1e-6)."""
+    g = dataclasses.replace(G1, nx=4, ny=4, nz=3, hx=4.0, hy=4.0, hz=4.0, nu=8, nv=6, pu=3.0, pv=3.0, n_views=8)
+    A = brute.matrix(g)
+    rng = np.random.default_rng(13)
+    ftrue = np.maximum(rng.standard_normal(g.n_vox), 0.0) * 0.02
+    Y = A @ ftrue + 0.01 * rng.standard_normal(A.shape[0])
+    xs, _ = nnls(A, Y, maxiter=10000)
+    d_star = np.mean((A @ xs - Y) ** 2)
+    res = O.reconstruct(g, Y.reshape(g.proj_shape), 0.0, [16000], 1)
+    d = np.mean((A @ res.f.ravel() - Y) ** 2)
+    e = abs(d - d_star) / d_star
+    return e < 1e-6 and res.f.min() >= 0.0, e
+
+
+def pin_resume():
+    """10 + 10 outer iterations through d_init equal 20 iterations (oracle: 1e-15)."""
+    Y = _cfg1_data()
+    t = O.schur_step(G1)
+    a = O.reconstruct(G1, Y, 0.05, [20], 1, step=t).f
+    b1 = O.reconstruct(G1, Y, 0.05, [10], 1, step=t).f
+    b = O.reconstruct(G1, Y, 0.05, [10], 1, step=t, d_init=b1).f
+    e = float(np.max(np.abs(a - b)) / np.max(np.abs(a)))
+    return e <= 1e-15, e
+
+
+def pin_constants():
+    """The solver defaults are the paper's line-search constants."""
+    d = O.DEFAULTS
+    a = GOLD["armijo"]
+    ok = d["armijo_c"] == a["c"] and d["backtrack"] == a["alpha"] and d["rof_tol"] == a["epsilon_relative"]
+    ex = GOLD["appendix_example"]
+    us, vs, ls, L = brute.appendix_uv(dataclasses.replace(G1, sad=-ex["S"][0], sdd=ex["L0"]), 0.0, ex["V"])
+    ok &= abs(us - ex["u_star"]) < 1e-9 and abs(vs - ex["v_star"]) < 1e-9 and abs(ls - ex["l_star"]) < 1e-9
+    ok &= abs(ex["L0"] * ls ** 2 / L ** 3 - ex["jacobian_L0_l2_over_L3"]) < 1e-12
+    return ok, None
+
+
+PINS = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_chords, pin_mass, pin_box,
+        pin_centroid, pin_continuum_adjoint, pin_tv_gradient, pin_tv_closed_forms, pin_transfers,
+        pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
+def test_pin(orc, pin):
+    ok, detail = pin()
+    assert ok, detail
+
+
+# Each planted mistake (see the fault switch in the oracle) with the pins expected to catch it.
+FAULTS = {
+    1: "3-D step weight replaced by the transverse step",
+    2: "detector u axis mirrored",
+    3: "parallel-beam z slope",
+    4: "transposed z weight wrong in P^T",
+    5: "zero instead of reflective z boundary",
+    6: "TV gradient misses the y terms",
+    7: "prolongation weights 1/2, 1/2",
+    8: "Armijo bound sign flipped",
+    9: "Step 1 goes uphill",
+    10: "restriction misses 1/8",
+    11: "voxel grid shifted half a voxel in x",
+}
+QUICK = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_centroid, pin_mass,
+         pin_tv_gradient, pin_tv_closed_forms, pin_transfers, pin_rof_armijo, pin_fbs_monotone]
+
+
+@pytest.mark.parametrize("fault", sorted(FAULTS), ids=[FAULTS[k] for k in sorted(FAULTS)])
+def test_planted_mistake_is_caught(orc, fault):
+    O.set_fault(fault)
+    try:
+        caught = []
+        for pin in QUICK:
+            try:
+                ok, _ = pin()
+            except Exception:
+                ok = False
+            if not ok:
+                caught.append(pin.__name__)
+                break
+    finally:
+        O.set_fault(0)
+    assert caught, "planted mistake %d (%s) passed every pin" % (fault, FAULTS[fault])
