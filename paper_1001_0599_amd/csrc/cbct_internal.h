@@ -1,0 +1,112 @@
+// Internal declarations shared by the libcbct host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "cbct.h"
+
+// Per (view, detector column) parameters of the column-coherent ray samples, prepared in FP64
+// on the host.  Sample k of column i lies at transverse distance tau_c + k*dtau from the
+// source; its voxel-index coordinates are (fx0 + k dfx, fy0 + k dfy), and detector row j
+// (q_j = j - (nv-1)/2) meets it at z-index gamma_k q_j + (nz-1)/2 with gamma_k = g0 + k dg.
+struct ColParams {
+    float fx0, fy0;  // index coordinates of sample 0 (closest approach of the column's line to the axis)
+    float dfx, dfy;  // index-coordinate step per sample
+    float g0, dg;    // z cells per detector row at sample k: gamma_k = g0 + k dg  (> 0)
+    float wsc, r2;   // ray step weight w_ij = wsc * sqrt(r2 + v_j^2)
+    int klo, khi;    // samples whose transverse position is within one voxel of the grid (inclusive)
+    int pad0, pad1;
+};
+static_assert(sizeof(ColParams) == 48, "ColParams layout");
+
+struct ViewParams {
+    float cs, sn;    // cos(theta), sin(theta)
+    float pad0, pad1;
+};
+
+// Tiling of the adjoint gather.
+constexpr int ADJ_TX = 16;     // voxel columns per tile in x (lanes)
+constexpr int ADJ_TY = 16;     // voxel columns per tile in y (lanes)
+constexpr int ADJ_CC = 8;      // detector columns per stage
+constexpr int ADJ_MAXR = 128;  // detector rows per prefix-sum stage
+
+struct Level {
+    int nx, ny, nz, nu, nv, nviews;
+    double hx, hy, hz, pu, pv, sad, sdd, dtau;
+    std::vector<double> angles;
+    // forward projector table geometry
+    int fwd_pad;   // zero cells on either side of the z range in the ray-sample tables
+    int fwd_kc;    // samples per table chunk
+    int fwd_tw;    // table rows (z cells incl. padding)
+    // adjoint gather sizing
+    int adj_tz;    // z cells per tile
+    int adj_maxnk; // max samples of one column inside one tile's support
+    double schur_t = 0.0;  // cached Schur-bound step (0: not computed yet)
+    // device tables
+    ColParams *d_cols = nullptr;   // [nviews][nu]
+    ViewParams *d_views = nullptr; // [nviews]
+    long nvox() const { return (long)nx * ny * nz; }
+    long nray() const { return (long)nviews * nv * nu; }
+};
+
+struct cbct_plan {
+    int device = 0;
+    int levels = 1;
+    int bin_detector = 1;
+    std::vector<Level> lv;
+};
+
+// error plumbing (thread-local message)
+cbct_status cbct_set_error(cbct_status s, const char *fmt, ...);
+cbct_status cbct_hip_error(hipError_t e, const char *what);
+#define CBCT_HIP(call)                                          \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return cbct_hip_error(e_, #call); \
+    } while (0)
+
+// kernel launchers (each checks its launch)
+cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_t, hipStream_t s);
+cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *y_sub, float *out,
+                                double *partials, hipStream_t s);
+cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
+                                float *out, hipStream_t s);
+
+// ---- solver pieces --------------------------------------------------------------------------
+constexpr int CBCT_RED_BLOCKS = 1024;  // work-groups of the fixed-size reduction grids
+constexpr int CBCT_TRIALS = 4;         // Armijo step sizes evaluated per trial pass
+
+// Device-side result of one Armijo search window (read by the host after each ROF iteration).
+struct RofControl {
+    double e0;       // E_R(u)
+    double G;        // mean(d^2)
+    double e_trial;  // E_R(u - s d) at the last tested step
+    double s;        // last tested step
+    int m;           // its backtracking exponent
+    int accepted;    // 1: step accepted, -1: no admissible step, 0: search continues at next_m0
+    int next_m0;
+    int pad;
+};
+
+int cbct_reduce_blocks(long n);
+cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
+                                double t, double *partials, double *sums, hipStream_t s);
+cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, double *partials, double *sum,
+                                  hipStream_t s);
+cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, const float *d, const float *g,
+                                 double t, double alpha, int m0, double *partials, double *sums, hipStream_t s);
+cbct_status cbct_launch_rof_decide(const double *sums, int m0, int forced_m, long nvox, double lambda, double t,
+                                   double c_armijo, double alpha, int max_bt, RofControl *ctl, hipStream_t s);
+cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ctl, long n, hipStream_t s);
+cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s);
+
+// multigrid transfers and small vector kernels
+cbct_status cbct_launch_prolong(const Level &coarse, const float *c, float *f, hipStream_t s);
+cbct_status cbct_launch_restrict(const Level &coarse, const float *f, float *c, hipStream_t s);
+cbct_status cbct_launch_bin(const Level &fine0, int factor, const float *y0, float *yl, hipStream_t s);
+cbct_status cbct_launch_clamp_columns(const Level &L, const float *u, float *f, float *f_t, hipStream_t s);
+cbct_status cbct_launch_fill(float *x, long n, float v, hipStream_t s);
+cbct_status cbct_launch_max(const float *x, long n, double *partials, double *out, hipStream_t s);

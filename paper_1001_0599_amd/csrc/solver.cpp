@@ -1,0 +1,391 @@
+// Reconstruction driver: Algorithm A1 of the paper (Section II.B) on every multigrid level
+// (Section II.C.3), with Step 2 solved by gradient descent and the Armijo rule (Eq. 5).
+//
+// Per outer iteration, on the caller's stream:
+//   P f - Y_l (residual epilogue of the projector)          -> r
+//   g = f - kappa P^T r (epilogue of the adjoint gather)     Step 1, kappa = t * 2 N_vox / N_rays
+//   u = g; ROF iterations: gradient pass, trial pass (4 step sizes), decision kernel, update
+//   f = max(u, 0) fused with the copy into the projector's layout  Step 3
+// The Armijo test and the stop test are evaluated on the device from FP64 sums; the host reads
+// the 64-byte decision record once per ROF iteration to steer the loop.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+#include <algorithm>
+
+#include "cbct_internal.h"
+
+namespace {
+
+std::mutex g_schur_mu;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off = align256(off + count * sizeof(T));
+        return p;
+    }
+};
+
+struct Bufs {
+    float *f, *ft, *g, *u, *d, *r;
+    float *ypyr[8];
+    double *part, *sums, *eng;
+    RofControl *ctl;
+    size_t bytes;
+};
+
+size_t partial_count(const cbct_plan *p) {
+    size_t m = (size_t)CBCT_RED_BLOCKS * (3 + 2 * CBCT_TRIALS);
+    for (const auto &L : p->lv) m = std::max(m, (size_t)L.nviews * L.nu);
+    return m;
+}
+
+Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws) {
+    Carver c{(char *)ws};
+    const Level &L0 = p->lv[0];
+    Bufs b{};
+    b.f = c.take<float>(L0.nvox());
+    b.ft = c.take<float>(L0.nvox());
+    b.g = c.take<float>(L0.nvox());
+    b.u = c.take<float>(L0.nvox());
+    b.d = c.take<float>(L0.nvox());
+    b.r = c.take<float>(std::max(L0.nray(), L0.nvox()));
+    for (int l = 0; l < 8; l++) b.ypyr[l] = nullptr;
+    for (int l = 1; l < levels; l++)
+        if (p->bin_detector) b.ypyr[l] = c.take<float>(p->lv[l].nray());
+    b.part = c.take<double>(partial_count(p));
+    b.sums = c.take<double>(64);
+    b.eng = c.take<double>(2 * (size_t)std::max(energy_slots, 1));
+    b.ctl = c.take<RofControl>(1);
+    b.bytes = c.off;
+    return b;
+}
+
+cbct_status check_params(const cbct_plan *p, const cbct_solve_params *pr, const char *who) {
+    if (!p || !pr) return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: NULL plan or params", who);
+    if (pr->levels < 1 || pr->levels > p->levels)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: params.levels %d not in [1, %d]", who, pr->levels, p->levels);
+    if (!pr->iters) return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: params.iters is NULL", who);
+    for (int l = 0; l < pr->levels; l++)
+        if (pr->iters[l] < 0 || pr->iters[l] > 100000)
+            return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: iters[%d] = %d out of range", who, l, pr->iters[l]);
+    if (!(pr->lambda >= 0.0) || !(pr->tv_eps > 0.0) || !(pr->armijo_c > 0.0) || !(pr->backtrack > 0.0) ||
+        !(pr->backtrack < 1.0) || !(pr->rof_tol >= 0.0) || pr->rof_max_iter < 0 || pr->rof_max_backtrack < 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: invalid line-search or TV parameters", who);
+    if (pr->replay_len < 0 || (pr->replay_len > 0 && !pr->replay))
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: replay_len > 0 needs a replay array", who);
+    return CBCT_OK;
+}
+
+int energy_slots(const cbct_solve_params *pr) {
+    int n = 0;
+    for (int l = 0; l < pr->levels; l++) n += pr->iters[l] + 1;
+    return n;
+}
+
+// Schur bound t = 1 / (kappa0 max(P 1) max(P^T 1)), cached per plan level
+cbct_status schur_step(cbct_plan *p, int level, const Bufs &b, hipStream_t s, double *t_out) {
+    Level &L = p->lv[level];
+    {
+        std::lock_guard<std::mutex> lk(g_schur_mu);
+        if (L.schur_t > 0.0) {
+            *t_out = L.schur_t;
+            return CBCT_OK;
+        }
+    }
+    cbct_status st;
+    if ((st = cbct_launch_fill(b.ft, L.nvox(), 1.0f, s))) return st;
+    if ((st = cbct_launch_forward(L, b.ft, nullptr, b.r, nullptr, s))) return st;
+    if ((st = cbct_launch_max(b.r, L.nray(), b.part, b.sums, s))) return st;
+    if ((st = cbct_launch_fill(b.r, L.nray(), 1.0f, s))) return st;
+    if ((st = cbct_launch_adjoint(L, b.r, nullptr, 0.0f, b.u, s))) return st;
+    if ((st = cbct_launch_max(b.u, L.nvox(), b.part, b.sums + 1, s))) return st;
+    double mx[2];
+    CBCT_HIP(hipMemcpyAsync(mx, b.sums, sizeof(mx), hipMemcpyDeviceToHost, s));
+    CBCT_HIP(hipStreamSynchronize(s));
+    const double kappa0 = 2.0 * (double)L.nvox() / (double)L.nray();
+    const double lip = kappa0 * mx[0] * mx[1];
+    if (!(lip > 0.0) || !std::isfinite(lip))
+        return cbct_set_error(CBCT_ERR_NONFINITE, "level %d: Schur bound %g is not positive and finite", level, lip);
+    std::lock_guard<std::mutex> lk(g_schur_mu);
+    L.schur_t = 1.0 / lip;
+    *t_out = L.schur_t;
+    return CBCT_OK;
+}
+
+struct TraceSink {
+    cbct_solve_stats *st;
+    void push(int level, int outer, int inner, int m, const RofControl &c) {
+        if (!st) return;
+        int k = st->trace_len;
+        if (st->trace && k < st->trace_cap) {
+            st->trace[4 * k + 0] = level;
+            st->trace[4 * k + 1] = outer;
+            st->trace[4 * k + 2] = inner;
+            st->trace[4 * k + 3] = m;
+            if (st->rof_e) {
+                st->rof_e[3 * k + 0] = c.e0;
+                st->rof_e[3 * k + 1] = c.e_trial;
+                st->rof_e[3 * k + 2] = c.G;
+            }
+        }
+        st->trace_len = k + 1;
+    }
+};
+
+// Step 2: u = ROF(g) from u = g.  `replay_pos` walks params.replay.
+cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, const Bufs &b, hipStream_t s,
+                     TraceSink &sink, int level, int outer, int *replay_pos) {
+    cbct_status st;
+    CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it < pr->rof_max_iter; it++) {
+        int forced = -2;  // free running
+        if (pr->replay && *replay_pos < pr->replay_len) forced = pr->replay[(*replay_pos)++];
+        if ((st = cbct_launch_tv_grad(L, pr->tv_eps, b.u, b.g, b.d, pr->lambda, t, b.part, b.sums, s))) return st;
+        RofControl c{};
+        if (forced == -1) {
+            // replayed decision: the search found no admissible step
+            double sums[3];
+            CBCT_HIP(hipMemcpyAsync(sums, b.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipStreamSynchronize(s));
+            const double inv_n = 1.0 / (double)L.nvox();
+            c.e0 = pr->lambda * sums[0] * inv_n + sums[1] * inv_n / (2.0 * t);
+            c.G = sums[2] * inv_n;
+            c.accepted = -1;
+            sink.push(level, outer, it, -1, c);
+            break;
+        }
+        int m0 = 0;
+        for (;;) {
+            if ((st = cbct_launch_tv_trial(L, pr->tv_eps, b.u, b.d, b.g, t, pr->backtrack, m0, b.part, b.sums + 3, s)))
+                return st;
+            if ((st = cbct_launch_rof_decide(b.sums, m0, forced >= 0 ? forced : -1, L.nvox(), pr->lambda, t,
+                                             pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, s)))
+                return st;
+            CBCT_HIP(hipMemcpyAsync(&c, b.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipStreamSynchronize(s));
+            if (c.accepted == 0 && c.next_m0 > m0) {
+                m0 = c.next_m0;
+                continue;
+            }
+            break;
+        }
+        if (!std::isfinite(c.e0) || !std::isfinite(c.G))
+            return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (level %d, outer %d)", level, outer);
+        sink.push(level, outer, it, c.accepted == 1 ? c.m : -1, c);
+        if (c.accepted != 1) break;  // Eq. 5 held for no step: keep u
+        if ((st = cbct_launch_axpy_step(b.u, b.d, b.ctl, L.nvox(), s))) return st;
+        if (c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol) break;
+    }
+    return CBCT_OK;
+}
+
+}  // namespace
+
+extern "C" void cbct_solve_params_default(cbct_solve_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->lambda = 0.05;
+    p->levels = 1;
+    p->step = 0.0;
+    p->tv_eps = 1e-5;
+    p->armijo_c = 0.01;
+    p->backtrack = 0.6;
+    p->rof_tol = 1e-3;
+    p->rof_max_iter = 50;
+    p->rof_max_backtrack = 30;
+}
+
+extern "C" cbct_status cbct_reconstruct_workspace_size(const cbct_plan *p, const cbct_solve_params *pr,
+                                                       size_t *bytes) {
+    cbct_status st = check_params(p, pr, "reconstruct_workspace_size");
+    if (st) return st;
+    if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct_workspace_size: NULL out");
+    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr).bytes;
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *pr, const float *d_y,
+                                        const float *d_init, float *d_out, void *d_ws, size_t ws_bytes,
+                                        cbct_stream_t stream, cbct_solve_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    cbct_status st = check_params(p, pr, "reconstruct");
+    if (st) return st;
+    if (!d_y || !d_out || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: NULL pointer");
+    const int levels = pr->levels;
+    const int nslots = energy_slots(pr);
+    Bufs b = carve(p, levels, nslots, d_ws);
+    if (ws_bytes < b.bytes)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: workspace %zu < %zu bytes", ws_bytes, b.bytes);
+    if (((uintptr_t)d_ws & 255) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) {
+        stats->trace_len = 0;
+        stats->energy_len = 0;
+        stats->replay_used = 0;
+        for (int l = 0; l < 8; l++) stats->t_used[l] = 0.0;
+    }
+    TraceSink sink{stats};
+    const bool want_energy = stats && stats->energy;
+    int replay_pos = 0;
+    int eslot = 0;
+    const Level &L0 = p->lv[0];
+
+    // coarsest start: 0, or d_init restricted level by level
+    {
+        const Level &Lc = p->lv[levels - 1];
+        if (d_init) {
+            const float *src = d_init;
+            float *bufs[2] = {b.g, b.u};
+            for (int l = 1; l < levels; l++) {
+                float *dst = (l == levels - 1) ? b.f : bufs[l & 1];
+                if ((st = cbct_launch_restrict(p->lv[l], src, dst, s))) return st;
+                src = dst;
+            }
+            if (levels == 1) CBCT_HIP(hipMemcpyAsync(b.f, d_init, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
+        } else {
+            if ((st = cbct_launch_fill(b.f, Lc.nvox(), 0.0f, s))) return st;
+        }
+    }
+    for (int l = levels - 1; l >= 0; l--) {
+        const Level &L = p->lv[l];
+        if (l < levels - 1) {
+            if ((st = cbct_launch_prolong(p->lv[l + 1], b.f, b.u, s))) return st;
+            std::swap(b.f, b.u);
+        }
+        const float *Yl = d_y;
+        if (l > 0 && p->bin_detector) {
+            if ((st = cbct_launch_bin(L0, 1 << l, d_y, b.ypyr[l], s))) return st;
+            Yl = b.ypyr[l];
+        }
+        double t = pr->step;
+        if (!(t > 0.0))
+            if ((st = schur_step(p, l, b, s, &t))) return st;
+        if (stats) stats->t_used[l] = t;
+        const float kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
+        if ((st = cbct_launch_to_columns(L, b.f, b.ft, s))) return st;
+        for (int k = 0; k <= pr->iters[l]; k++) {
+            const bool last = (k == pr->iters[l]);
+            if (last && !want_energy) break;
+            // residual r = P f - Y_l and its sum of squares
+            if ((st = cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s))) return st;
+            if (want_energy) {
+                if ((st = cbct_launch_sum_rows(b.part, L.nviews * L.nu, 1, b.eng + 2 * eslot, s))) return st;
+                if ((st = cbct_launch_tv_energy(L, pr->tv_eps, b.f, b.part, b.eng + 2 * eslot + 1, s))) return st;
+                eslot++;
+            }
+            if (last) break;
+            // Step 1
+            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, s))) return st;
+            // Step 2
+            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
+            // Step 3
+            if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s))) return st;
+        }
+    }
+    CBCT_HIP(hipMemcpyAsync(d_out, b.f, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
+    if (stats) {
+        stats->replay_used = replay_pos;
+        if (want_energy) {
+            std::vector<double> e(2 * (size_t)eslot);
+            if (eslot) CBCT_HIP(hipMemcpyAsync(e.data(), b.eng, sizeof(double) * e.size(), hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipStreamSynchronize(s));
+            int idx = 0;
+            for (int l = levels - 1; l >= 0; l--) {
+                const Level &L = p->lv[l];
+                for (int k = 0; k <= pr->iters[l]; k++, idx++) {
+                    const double E = e[2 * idx] / (double)L.nray() + pr->lambda * e[2 * idx + 1] / (double)L.nvox();
+                    if (stats->energy_len < stats->energy_cap) stats->energy[stats->energy_len] = E;
+                    stats->energy_len++;
+                }
+            }
+        }
+        CBCT_HIP(hipStreamSynchronize(s));
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_tv_prox_workspace_size(const cbct_plan *p, int level, size_t *bytes) {
+    if (!p || !bytes || level < 0 || level >= p->levels)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox_workspace_size: bad arguments");
+    cbct_solve_params pr;
+    cbct_solve_params_default(&pr);
+    int it = 0;
+    pr.iters = &it;
+    *bytes = carve(p, 1, 1, nullptr).bytes;
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_params *pr, const float *d_g,
+                                    float *d_u, void *d_ws, size_t ws_bytes, cbct_stream_t stream,
+                                    cbct_solve_stats *stats) {
+    if (!p || !pr || !d_g || !d_u || !d_ws || level < 0 || level >= p->levels)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: bad arguments");
+    if (!(pr->step > 0.0)) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: params.step (t) must be > 0");
+    Bufs b = carve(p, 1, 1, d_ws);
+    if (ws_bytes < b.bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const Level &L = p->lv[level];
+    if (stats) stats->trace_len = 0;
+    TraceSink sink{stats};
+    int pos = 0;
+    CBCT_HIP(hipMemcpyAsync(b.g, d_g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+    cbct_status st = rof_loop(L, pr, pr->step, b, s, sink, level, 0, &pos);
+    if (st) return st;
+    CBCT_HIP(hipMemcpyAsync(d_u, b.u, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+    if (stats) stats->replay_used = pos;
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_tv_energy_grad(cbct_plan *p, int level, double tv_eps, const float *d_f, float *d_grad,
+                                           double *h_sum, void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
+    if (!p || !d_f || !d_ws || level < 0 || level >= p->levels || !(tv_eps > 0.0))
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad: bad arguments");
+    const size_t need = align256(sizeof(double) * (CBCT_RED_BLOCKS * 3 + 8));
+    if (ws_bytes < need) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad: workspace < %zu bytes", need);
+    const Level &L = p->lv[level];
+    hipStream_t s = (hipStream_t)stream;
+    double *part = (double *)d_ws, *sums = part + CBCT_RED_BLOCKS * 3;
+    cbct_status st;
+    if (d_grad) st = cbct_launch_tv_grad(L, tv_eps, d_f, nullptr, d_grad, 0.0, 1.0, part, sums, s);
+    else st = cbct_launch_tv_energy(L, tv_eps, d_f, part, sums, s);
+    if (st) return st;
+    if (h_sum) {
+        CBCT_HIP(hipMemcpyAsync(h_sum, sums, sizeof(double), hipMemcpyDeviceToHost, s));
+        CBCT_HIP(hipStreamSynchronize(s));
+    }
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_prolong(const cbct_plan *p, int coarse_level, const float *d_c, float *d_f,
+                                    cbct_stream_t stream) {
+    if (!p || !d_c || !d_f || coarse_level < 1 || coarse_level >= p->levels)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "prolong: bad arguments");
+    return cbct_launch_prolong(p->lv[coarse_level], d_c, d_f, (hipStream_t)stream);
+}
+
+extern "C" cbct_status cbct_restrict(const cbct_plan *p, int fine_level, const float *d_f, float *d_c,
+                                     cbct_stream_t stream) {
+    if (!p || !d_c || !d_f || fine_level < 0 || fine_level + 1 >= p->levels)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "restrict: bad arguments");
+    return cbct_launch_restrict(p->lv[fine_level + 1], d_f, d_c, (hipStream_t)stream);
+}
+
+extern "C" cbct_status cbct_bin_detector(const cbct_plan *p, int level, const float *d_y0, float *d_yl,
+                                         cbct_stream_t stream) {
+    if (!p || !d_y0 || !d_yl || level < 1 || level >= p->levels || !p->bin_detector)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "bin_detector: bad arguments (level >= 1, plan with binning)");
+    return cbct_launch_bin(p->lv[0], 1 << level, d_y0, d_yl, (hipStream_t)stream);
+}

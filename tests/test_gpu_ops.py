@@ -1,0 +1,143 @@
+"""Parity of the HIP forward projector P and adjoint P^T with the FP64 oracle.
+
+Bar: relative L2 <= 1e-4 on projections and adjoint volumes (FP32 GPU vs FP64 oracle).
+Full-size workloads are compared on sampled rays / voxels that the oracle computes
+one by one, plus the adjoint identity in FP64 accumulation at full size."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import cbct_synth as S
+import oracle as O
+from tests.gpu_util import announce, rel_l2, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+G1 = S.config_geometry("cfg1")
+CASES = {
+    "cfg1": G1,
+    # ragged: sizes not multiples of the tiles, odd detector rows, nz not a multiple of 4
+    "ragged": dataclasses.replace(G1, nx=23, ny=19, nz=13, nu=37, nv=29, n_views=7),
+    "anisotropic": dataclasses.replace(G1, nx=40, ny=24, nz=18, hx=1.5, hy=2.5, hz=3.0, nu=50, nv=31, pu=1.3,
+                                       pv=2.1, n_views=5, angles=(0.1, 1.0, 2.5, 3.9, 5.9)),
+    "axis_aligned": dataclasses.replace(G1, n_views=4, angles=(0.0, np.pi / 2, np.pi, 1.5 * np.pi)),
+    "tiny": dataclasses.replace(G1, nx=2, ny=3, nz=1, nu=3, nv=1, n_views=2),
+    "cfg4_one": S.config_geometry("cfg4"),
+}
+
+
+def _plan(g, levels=1):
+    from paper_1001_0599_amd.ops import Plan
+    return Plan(g, levels=levels)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_matches_oracle(name):
+    g = CASES[name]
+    announce("forward %s %s" % (name, g.vol_shape))
+    plan = _plan(g)
+    for kind, vol in (("phantom", S.voxelize(g, S.make_phantom(g, 11), 2) if g.nz > 4 else None),
+                      ("random", S.random_volume(g, 5))):
+        if vol is None:
+            continue
+        got = to_np(plan.forward(to_gpu(vol)))
+        want = O.forward(g, vol)
+        e = rel_l2(got, want)
+        assert e < TOL, (name, kind, e)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_matches_oracle(name):
+    g = CASES[name]
+    announce("adjoint %s %s" % (name, g.proj_shape))
+    plan = _plan(g)
+    for kind, y in (("random", S.random_projections(g, 6)), ("signed", S.random_projections(g, 7, "normal"))):
+        got = to_np(plan.adjoint(to_gpu(y)))
+        want = O.adjoint(g, y)
+        e = rel_l2(got, want)
+        assert e < TOL, (name, kind, e)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "cfg4_one"])
+def test_gpu_adjoint_identity(name):
+    g = CASES[name]
+    plan = _plan(g)
+    x = S.random_volume(g, 8, "normal")
+    y = S.random_projections(g, 9, "normal")
+    a = float(np.vdot(to_np(plan.forward(to_gpu(x))), y))
+    b = float(np.vdot(x, to_np(plan.adjoint(to_gpu(y)))))
+    assert abs(a - b) / abs(a) < 2e-5, (a, b)
+
+
+def test_forward_full_size_sampled():
+    """512x512x64, 40 views, 512x384 detector (both multigrid levels): sampled rays."""
+    g = S.config_geometry("cfg2")
+    announce("forward full-size cfg2 sampled")
+    plan = _plan(g, levels=2)
+    rng = np.random.default_rng(0)
+    ph = S.make_phantom(g, 21)
+    for level in (0, 1):
+        gl = S.level_geometry(g, level)
+        vol = S.voxelize(gl, ph, 1) + 0.002 * S.random_volume(gl, 3)
+        got = to_np(plan.forward(to_gpu(vol), level=level)).ravel()
+        rays = rng.choice(got.size, 3000, replace=False)
+        want = O.forward_rays(gl, vol, rays)
+        e = rel_l2(got[rays], want)
+        assert e < TOL, (level, e)
+
+
+def test_adjoint_full_size_sampled():
+    g = S.config_geometry("cfg2")
+    announce("adjoint full-size cfg2 sampled")
+    plan = _plan(g, levels=2)
+    rng = np.random.default_rng(1)
+    for level in (0, 1):
+        gl = S.level_geometry(g, level)
+        y = S.random_projections(gl, 11)
+        got = to_np(plan.adjoint(to_gpu(y), level=level)).ravel()
+        # sample inside the field of view (the rest is checked by the identity test below)
+        vox = rng.choice(got.size, 400, replace=False)
+        vox = vox[got[vox] != 0][:150]
+        want = O.adjoint_voxels(gl, y, vox)
+        e = rel_l2(got[vox], want)
+        assert e < TOL, (level, e)
+
+
+def test_full_size_adjoint_identity():
+    """<Px, y> = <x, P^T y> at 512x512x64 / 40 views: relative 2e-5 for non-negative inputs,
+    and |<Px,y> - <x,P^T y>| <= 1e-6 |Px| |y| for signed inputs (their inner products cancel)."""
+    g = S.config_geometry("cfg2")
+    plan = _plan(g)
+    for kind, tol in (("uniform", 2e-5), ("normal", 1e-6)):
+        x = to_gpu(S.random_volume(g, 12, kind))
+        y = to_gpu(S.random_projections(g, 13, kind))
+        px = plan.forward(x).double()
+        a = torch.sum(px * y.double()).item()
+        b = torch.sum(x.double() * plan.adjoint(y).double()).item()
+        scale = abs(a) if kind == "uniform" else (torch.linalg.norm(px) * torch.linalg.norm(y.double())).item()
+        assert abs(a - b) / scale < tol, (kind, a, b)
+
+
+def test_deterministic():
+    g = CASES["ragged"]
+    plan = _plan(g)
+    x = to_gpu(S.random_volume(g, 14))
+    y = to_gpu(S.random_projections(g, 15))
+    assert torch.equal(plan.forward(x), plan.forward(x))
+    assert torch.equal(plan.adjoint(y), plan.adjoint(y))
+
+
+def test_input_validation():
+    from paper_1001_0599_amd import _lib
+    plan = _plan(G1)
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((3, 3, 3), device="cuda"))
+    x = torch.zeros(G1.vol_shape, device="cuda")
+    y = torch.zeros(G1.proj_shape, device="cuda")
+    L = _lib.lib()
+    assert L.cbct_forward(plan.handle, 1, x.data_ptr(), y.data_ptr(), x.data_ptr(), 4 * x.numel(), None) == 1
+    assert L.cbct_forward(plan.handle, 0, x.data_ptr(), y.data_ptr(), x.data_ptr(), 16, None) == 1
+    assert L.cbct_adjoint(plan.handle, -1, y.data_ptr(), x.data_ptr(), None) == 1
