@@ -238,6 +238,41 @@ def analytic_projections(g: Geometry, phantom: Sequence[Ellipsoid], views=None) 
     return p
 
 
+def analytic_projections_torch(g: Geometry, phantom: Sequence[Ellipsoid], device, dtype=None):
+    """The same exact line integrals as analytic_projections, evaluated with torch on `device`
+    (float64 by default): used to synthesise large request streams quickly."""
+    import torch
+    dtype = dtype or torch.float64
+    S, D = ray_endpoints(g)
+    S = torch.as_tensor(S, dtype=dtype, device=device)[:, None, None, :]
+    D = torch.as_tensor(D, dtype=dtype, device=device)
+    d = D - S
+    d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
+    p = torch.zeros(D.shape[:-1], dtype=dtype, device=device)
+    for e in phantom:
+        c, M = _ellipsoid_frame(e)
+        c = torch.as_tensor(c, dtype=dtype, device=device)
+        M = torch.as_tensor(M, dtype=dtype, device=device)
+        o = (S - c) @ M.T
+        dd = d @ M.T
+        a = (dd * dd).sum(-1)
+        b = 2.0 * (o * dd).sum(-1)
+        cc = (o * o).sum(-1) - 1.0
+        disc = b * b - 4.0 * a * cc
+        p += e.dmu * torch.where(disc > 0, torch.sqrt(torch.clamp(disc, min=0.0)) / a, torch.zeros_like(disc))
+    return p
+
+
+def poisson_log_torch(p, I0: float, seed: int):
+    """Y = -ln(max(N, 1) / I0), N ~ Poisson(I0 exp(-p)), drawn with a seeded torch generator on
+    p's device (a different stream of draws than poisson_log)."""
+    import torch
+    gen = torch.Generator(device=p.device)
+    gen.manual_seed(int(seed))
+    N = torch.poisson(I0 * torch.exp(-p), generator=gen)
+    return -torch.log(torch.clamp(N, min=1.0) / I0)
+
+
 def voxelize(g: Geometry, phantom: Sequence[Ellipsoid], supersample: int = 4) -> np.ndarray:
     """Ground-truth attenuation on the grid, each voxel the mean of supersample^3 points."""
     n = supersample

@@ -92,6 +92,11 @@ cbct_status cbct_forward_workspace_size(const cbct_plan *plan, int level, size_t
 cbct_status cbct_forward(const cbct_plan *plan, int level, const float *d_vol, float *d_proj, void *d_ws,
                          size_t ws_bytes, cbct_stream_t stream);
 
+/* The same P for a volume already in the projector's column-major layout [ny][nx][nz]
+ * (z fastest), as the reconstruction keeps it: no workspace, one kernel. */
+cbct_status cbct_forward_columns(const cbct_plan *plan, int level, const float *d_vol_cols, float *d_proj,
+                                 cbct_stream_t stream);
+
 /* Adjoint P^T (exact transpose of cbct_forward; Section II.C.2): d_vol = P_level^T d_proj.
  * No workspace; the gather writes every voxel of d_vol once and uses no atomics. */
 cbct_status cbct_adjoint(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
@@ -177,6 +182,54 @@ cbct_status cbct_tv_energy_grad(cbct_plan *plan, int level, double tv_eps, const
 cbct_status cbct_prolong(const cbct_plan *plan, int coarse_level, const float *d_c, float *d_f, cbct_stream_t stream);
 cbct_status cbct_restrict(const cbct_plan *plan, int fine_level, const float *d_f, float *d_c, cbct_stream_t stream);
 cbct_status cbct_bin_detector(const cbct_plan *plan, int level, const float *d_y0, float *d_yl, cbct_stream_t stream);
+
+/* ---- Serving: continuous admission of reconstruction requests ----------------------------
+ *
+ * A server owns `max_slots` worker slots, each with its own non-blocking HIP stream on the device
+ * that was current at creation.  Requests (any geometry, any params without replay) queue FIFO;
+ * the head starts as soon as a slot is free and (device bytes in use + its bytes) <= the budget,
+ * also while other requests run, so admitted solves overlap on the GPU.  A request's bytes are
+ * its reconstruction workspace, its plan tables and, for host projections, their device copy.
+ * Results are bitwise identical to a solo cbct_reconstruct of the same request.  Device memory
+ * is pooled and plans are cached by geometry for the server's lifetime.  All server calls are
+ * thread-safe. */
+typedef struct cbct_server cbct_server;
+
+/* INVALID_ARG for budget 0 or max_slots outside 1..256. */
+cbct_status cbct_server_create(size_t hbm_budget_bytes, int max_slots, cbct_server **out);
+
+/* Queue one reconstruction.  y: level-0 projections [n_views][nv][nu], device memory (y_on_host = 0,
+ * must stay valid until the request is done) or host memory (y_on_host = 1, copied when the
+ * request starts); d_out: device volume [nz][ny][nx] written when the request is done.
+ * params->iters is copied; the plan is built with detector binning.  INVALID_ARG for an invalid
+ * geometry or params (checked here, before queueing), BUDGET when the request alone exceeds the
+ * budget. */
+cbct_status cbct_server_submit(cbct_server *server, const cbct_geometry_desc *geom, const cbct_solve_params *params,
+                               const float *y, int y_on_host, float *d_out, uint64_t *ticket);
+
+/* done = 1 once the request finished; result = its status; latency_s = submit-to-done seconds
+ * (host steady clock), -1 while running.  NOT_FOUND for an unknown ticket. */
+cbct_status cbct_server_poll(cbct_server *server, uint64_t ticket, int *done, cbct_status *result, double *latency_s);
+
+/* submit, start and done instants (seconds on the host steady clock) of a finished request */
+cbct_status cbct_server_request_times(cbct_server *server, uint64_t ticket, double times[3]);
+
+/* Blocks until the queue is empty and no request runs; returns the first failed request's status. */
+cbct_status cbct_server_wait_all(cbct_server *server);
+
+/* Current and peak device bytes in use, running requests, queue length, completed requests. */
+cbct_status cbct_server_stats(cbct_server *server, size_t *in_use, size_t *peak_in_use, int *running,
+                              int *peak_running, int *queued, uint64_t *completed);
+
+/* Stops the workers after their current request (queued requests are dropped) and frees the
+ * server's device memory and plans. */
+void cbct_server_destroy(cbct_server *server);
+
+/* Scheduler test hooks: a server whose requests sleep `seconds` instead of running on the GPU
+ * (same admission and slot logic; no device memory is touched). */
+cbct_status cbct_server_create_simulated(size_t hbm_budget_bytes, int max_slots, cbct_server **out);
+cbct_status cbct_server_submit_simulated(cbct_server *server, const cbct_geometry_desc *geom,
+                                         const cbct_solve_params *params, double seconds, uint64_t *ticket);
 
 /* Human-readable name of a status, and the calling thread's last error message. */
 const char *cbct_status_string(cbct_status s);

@@ -57,6 +57,7 @@ _SIG = [
     ("cbct_plan_level_dims", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
     ("cbct_forward_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
     ("cbct_forward", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
+    ("cbct_forward_columns", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_adjoint", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_solve_params_default", None, [C.POINTER(SolveParams)]),
     ("cbct_reconstruct_workspace_size", C.c_int, [_VP, C.POINTER(SolveParams), C.POINTER(C.c_size_t)]),
@@ -70,6 +71,18 @@ _SIG = [
     ("cbct_prolong", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_restrict", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_bin_detector", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
+    ("cbct_server_create", C.c_int, [C.c_size_t, C.c_int, C.POINTER(_VP)]),
+    ("cbct_server_submit", C.c_int, [_VP, C.POINTER(GeometryDesc), C.POINTER(SolveParams), _VP, C.c_int, _VP,
+                                     C.POINTER(C.c_uint64)]),
+    ("cbct_server_poll", C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    ("cbct_server_request_times", C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_double)]),
+    ("cbct_server_wait_all", C.c_int, [_VP]),
+    ("cbct_server_stats", C.c_int, [_VP, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
+    ("cbct_server_destroy", None, [_VP]),
+    ("cbct_server_create_simulated", C.c_int, [C.c_size_t, C.c_int, C.POINTER(_VP)]),
+    ("cbct_server_submit_simulated", C.c_int, [_VP, C.POINTER(GeometryDesc), C.POINTER(SolveParams), C.c_double,
+                                               C.POINTER(C.c_uint64)]),
     ("cbct_status_string", C.c_char_p, [C.c_int]),
     ("cbct_last_error", C.c_char_p, []),
 ]

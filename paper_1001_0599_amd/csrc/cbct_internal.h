@@ -18,7 +18,7 @@ struct ColParams {
     float g0, dg;    // z cells per detector row at sample k: gamma_k = g0 + k dg  (> 0)
     float wsc, r2;   // ray step weight w_ij = wsc * sqrt(r2 + v_j^2)
     int klo, khi;    // samples whose transverse position is within one voxel of the grid (inclusive)
-    int pad0, pad1;
+    float idfx, idfy; // 1/dfx, 1/dfy (0 when the step along that axis vanishes)
 };
 static_assert(sizeof(ColParams) == 48, "ColParams layout");
 
@@ -30,8 +30,17 @@ struct ViewParams {
 // Tiling of the adjoint gather.
 constexpr int ADJ_TX = 16;     // voxel columns per tile in x (lanes)
 constexpr int ADJ_TY = 16;     // voxel columns per tile in y (lanes)
-constexpr int ADJ_CC = 8;      // detector columns per stage
-constexpr int ADJ_MAXR = 128;  // detector rows per prefix-sum stage
+constexpr int ADJ_MAXL = 12;   // projection loads per thread per LDS chunk (cc_max * r_max <= 256 * ADJ_MAXL)
+
+// Sizes the adjoint kernel needs per level (computed by the plan builder).
+struct AdjArgs {
+    int nx, ny, nz, nu, nv, nviews;
+    float hx, hy, hz, pu, pv, sad, sdd;
+    int maxnk;   // max samples of one column inside one tile's support
+    int cc_max;  // detector columns per LDS chunk (<= 64)
+    int r_max;   // detector rows per LDS chunk
+    int s_max;   // slot capacity of one chunk
+};
 
 struct Level {
     int nx, ny, nz, nu, nv, nviews;
@@ -43,7 +52,7 @@ struct Level {
     int fwd_tw;    // table rows (z cells incl. padding)
     // adjoint gather sizing
     int adj_tz;    // z cells per tile
-    int adj_maxnk; // max samples of one column inside one tile's support
+    AdjArgs adj;
     double schur_t = 0.0;  // cached Schur-bound step (0: not computed yet)
     // device tables
     ColParams *d_cols = nullptr;   // [nviews][nu]
@@ -70,10 +79,13 @@ cbct_status cbct_hip_error(hipError_t e, const char *what);
 
 // kernel launchers (each checks its launch)
 cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_t, hipStream_t s);
+// y_sub == NULL: out = P f.  Otherwise residual mode: out = w * (P f - y_sub) (the ray weight
+// applied, ready for the pre-weighted adjoint) and partials[view * nu + i] = sum (P f - y_sub)^2.
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *y_sub, float *out,
                                 double *partials, hipStream_t s);
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
-                                float *out, hipStream_t s);
+                                float *out, hipStream_t s, bool preweighted = false);
+size_t cbct_adjoint_lds_bytes(const AdjArgs &A, int tz);
 
 // ---- solver pieces --------------------------------------------------------------------------
 constexpr int CBCT_RED_BLOCKS = 1024;  // work-groups of the fixed-size reduction grids

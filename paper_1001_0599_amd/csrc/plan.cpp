@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -59,6 +60,101 @@ static void sample_range_1d(double f0, double df, int n, double &lo, double &hi)
     double a = (-1.0 - f0) / df, b = ((double)n - f0) / df;
     lo = std::min(a, b);
     hi = std::max(a, b);
+}
+
+// Sizes of the adjoint gather's LDS chunks: an FP64 replica of the kernel's per-tile column,
+// row and sample ranges (the kernel's FP32 ranges may differ by one at the margins, which the
+// capacities below absorb: the kernel also splits any range that does not fit into chunks).
+static cbct_status size_adjoint(Level &L, const std::vector<ColParams> &cols) {
+    L.adj_tz = L.nz >= 16 ? 16 : 8;
+    const int tz = L.adj_tz;
+    AdjArgs &A = L.adj;
+    A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
+    A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
+    A.sad = (float)L.sad; A.sdd = (float)L.sdd;
+    const double diag = std::sqrt(std::pow((ADJ_TX + 1) * L.hx, 2) + std::pow((ADJ_TY + 1) * L.hy, 2));
+    A.maxnk = (int)std::ceil(diag / L.dtau) + 4;
+    const double cx = 0.5 * (L.nx - 1), cy = 0.5 * (L.ny - 1), cz = 0.5 * (L.nz - 1);
+    const double iu = 0.5 * (L.nu - 1), iv = 0.5 * (L.nv - 1);
+    const int ntx = (L.nx + ADJ_TX - 1) / ADJ_TX, nty = (L.ny + ADJ_TY - 1) / ADJ_TY, ntz = (L.nz + tz - 1) / tz;
+    int max_rows = 1, max_cols = 1;
+    // per (view, xy tile): per-column slot counts; keep the max over sliding windows later
+    std::vector<std::vector<int>> counts;
+    counts.reserve((size_t)L.nviews * ntx * nty);
+    for (int v = 0; v < L.nviews; v++) {
+        const double cs = std::cos(L.angles[v]), sn = std::sin(L.angles[v]);
+        for (int ty = 0; ty < nty; ty++)
+            for (int tx = 0; tx < ntx; tx++) {
+                const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY;
+                const int a1 = std::min(a0 + ADJ_TX, L.nx) - 1, b1 = std::min(b0 + ADJ_TY, L.ny) - 1;
+                const double xl = (a0 - 1 - cx) * L.hx, xh = (a1 + 1 - cx) * L.hx;
+                const double yl = (b0 - 1 - cy) * L.hy, yh = (b1 + 1 - cy) * L.hy;
+                double umin = 1e300, umax = -1e300, dmin = 1e300, dmax = -1e300;
+                for (int q = 0; q < 4; q++) {
+                    const double x = (q & 1) ? xh : xl, y = (q & 2) ? yh : yl;
+                    const double d = x * cs + y * sn + L.sad;
+                    const double u = L.sdd * (x * sn - y * cs) / d;
+                    umin = std::min(umin, u);
+                    umax = std::max(umax, u);
+                    dmin = std::min(dmin, d);
+                    dmax = std::max(dmax, d);
+                }
+                const int i0 = std::max(0, (int)std::floor(umin / L.pu + iu) - 2);
+                const int i1 = std::min(L.nu - 1, (int)std::ceil(umax / L.pu + iu) + 2);
+                if (i0 > i1) continue;
+                max_cols = std::max(max_cols, i1 - i0 + 1);
+                for (int tzi = 0; tzi < ntz; tzi++) {
+                    const int c0 = tzi * tz, c1 = std::min(c0 + tz, L.nz) - 1;
+                    const double zl = (c0 - 1 - cz) * L.hz, zh = (c1 + 1 - cz) * L.hz;
+                    const double vmin = std::min(L.sdd * zl / dmin, L.sdd * zl / dmax);
+                    const double vmax = std::max(L.sdd * zh / dmin, L.sdd * zh / dmax);
+                    const int j0 = std::max(0, (int)std::floor(vmin / L.pv + iv) - 2);
+                    const int j1 = std::min(L.nv - 1, (int)std::ceil(vmax / L.pv + iv) + 2);
+                    if (j0 <= j1) max_rows = std::max(max_rows, j1 - j0 + 1);
+                }
+                std::vector<int> cnt(i1 - i0 + 1, 0);
+                for (int i = i0; i <= i1; i++) {
+                    const ColParams &cp = cols[(size_t)v * L.nu + i];
+                    double lo = cp.klo, hi = cp.khi;
+                    const double fx0 = cp.fx0, fy0 = cp.fy0, dfx = cp.dfx, dfy = cp.dfy;
+                    if (std::fabs(dfx) > 1e-12) {
+                        const double ka = (a0 - 1 - fx0) / dfx, kb = (a1 + 1 - fx0) / dfx;
+                        lo = std::max(lo, std::min(ka, kb) - 1.0);
+                        hi = std::min(hi, std::max(ka, kb) + 1.0);
+                    }
+                    if (std::fabs(dfy) > 1e-12) {
+                        const double ka = (b0 - 1 - fy0) / dfy, kb = (b1 + 1 - fy0) / dfy;
+                        lo = std::max(lo, std::min(ka, kb) - 1.0);
+                        hi = std::min(hi, std::max(ka, kb) + 1.0);
+                    }
+                    const int n = (int)std::floor(hi) - (int)std::ceil(lo) + 1;
+                    cnt[i - i0] = std::min(std::max(n, 0) + 2, A.maxnk);
+                }
+                counts.push_back(std::move(cnt));
+            }
+    }
+    A.r_max = std::min(max_rows + 4, 256);
+    const size_t budget = 52 * 1024;
+    for (int cc : {64, 48, 40, 32, 24, 20, 16, 12, 8, 4}) {
+        if (cc > 64) continue;
+        int smax = 0;
+        for (const auto &cnt : counts) {
+            int win = 0;
+            for (size_t q = 0; q < cnt.size(); q++) {
+                win += cnt[q];
+                if (q >= (size_t)cc) win -= cnt[q - cc];
+                smax = std::max(smax, win);
+            }
+        }
+        A.cc_max = std::min(cc, std::max(max_cols + 4, 4));
+        A.r_max = std::min(std::min(max_rows + 4, 256), (256 * ADJ_MAXL) / A.cc_max);
+        A.s_max = std::max(smax, 1);
+        if (cbct_adjoint_lds_bytes(A, tz) <= budget || cc == 4) break;
+    }
+    if (cbct_adjoint_lds_bytes(A, tz) > 64 * 1024)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint tiles need %zu bytes of LDS (geometry too extreme)",
+                              cbct_adjoint_lds_bytes(A, tz));
+    return CBCT_OK;
 }
 
 static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Level &L) {
@@ -120,7 +216,8 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
             c.r2 = (float)r2;
             c.klo = klo;
             c.khi = khi;
-            c.pad0 = c.pad1 = 0;
+            c.idfx = std::fabs(dfx) > 1e-12 ? (float)(1.0 / dfx) : 0.0f;
+            c.idfy = std::fabs(dfy) > 1e-12 ? (float)(1.0 / dfy) : 0.0f;
             if (khi >= klo) {
                 // up to one chunk (<= 32 samples) is appended below to fill whole chunks
                 double gmax = (tau_c + (khi + 32) * L.dtau) * L.pv / (r * L.hz);
@@ -142,12 +239,16 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     for (auto &c : cols)
         if (c.khi >= c.klo) c.khi = c.klo + ((c.khi - c.klo + L.fwd_kc) / L.fwd_kc) * L.fwd_kc - 1;
     // adjoint tiling
-    L.adj_tz = L.nz >= 16 ? 16 : 8;
-    const double diag = std::sqrt(std::pow((ADJ_TX + 1) * L.hx, 2) + std::pow((ADJ_TY + 1) * L.hy, 2));
-    L.adj_maxnk = (int)std::ceil(diag / L.dtau) + 4;
-    if ((size_t)ADJ_CC * L.adj_maxnk > 1024)
-        return cbct_set_error(CBCT_ERR_INVALID_ARG, "level %d: sample spacing too fine for the adjoint tiles", l);
+    cbct_status sz = size_adjoint(L, cols);
+    if (sz) return sz;
 
+    if (std::getenv("CBCT_PLAN_REPORT"))
+        std::fprintf(stderr,
+                     "[cbct plan] level %d: %dx%dx%d voxels, %d views %dx%d; fwd pad %d kc %d lds %zu; "
+                     "adj tz %d cc %d rows %d slots %d maxnk %d lds %zu\n",
+                     l, L.nx, L.ny, L.nz, L.nviews, L.nu, L.nv, L.fwd_pad, L.fwd_kc,
+                     (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4, L.adj_tz, L.adj.cc_max, L.adj.r_max, L.adj.s_max,
+                     L.adj.maxnk, cbct_adjoint_lds_bytes(L.adj, L.adj_tz));
     CBCT_HIP(hipMalloc((void **)&L.d_cols, sizeof(ColParams) * cols.size()));
     CBCT_HIP(hipMalloc((void **)&L.d_views, sizeof(ViewParams) * views.size()));
     CBCT_HIP(hipMemcpy(L.d_cols, cols.data(), sizeof(ColParams) * cols.size(), hipMemcpyHostToDevice));
@@ -242,6 +343,8 @@ extern "C" cbct_status cbct_forward(const cbct_plan *p, int level, const float *
     if (ws_bytes < (size_t)L.nvox() * sizeof(float))
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: workspace %zu < %zu bytes", ws_bytes,
                               (size_t)L.nvox() * sizeof(float));
+    if (((uintptr_t)d_ws & 15) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: workspace must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     s = cbct_launch_to_columns(L, d_vol, (float *)d_ws, st);
     if (s) return s;
@@ -254,4 +357,14 @@ extern "C" cbct_status cbct_adjoint(const cbct_plan *p, int level, const float *
     if (s) return s;
     if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: NULL pointer");
     return cbct_launch_adjoint(p->lv[level], d_proj, nullptr, 0.0f, d_vol, (hipStream_t)stream);
+}
+
+extern "C" cbct_status cbct_forward_columns(const cbct_plan *p, int level, const float *d_vol_cols, float *d_proj,
+                                            cbct_stream_t stream) {
+    cbct_status s = check_level(p, level, "forward_columns");
+    if (s) return s;
+    if (!d_vol_cols || !d_proj) return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: NULL pointer");
+    if (((uintptr_t)d_vol_cols & 15) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: volume must be 16-byte aligned");
+    return cbct_launch_forward(p->lv[level], d_vol_cols, nullptr, d_proj, nullptr, (hipStream_t)stream);
 }

@@ -133,8 +133,15 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
         float sb[NPT];
+        bool live = false;  // does any of this thread's rays meet the slab within the chunk?
 #pragma unroll
-        for (int p = 0; p < NPT; p++) sb[p] = fmaf((float)k0, ds[p], s0[p]);
+        for (int p = 0; p < NPT; p++) {
+            sb[p] = fmaf((float)k0, ds[p], s0[p]);
+            const float se = fmaf((float)(KC - 1), ds[p], sb[p]);
+            live |= fmaxf(sb[p], se) >= (float)(off - 1) && fminf(sb[p], se) < (float)(off + nz);
+        }
+        // rays outside the slab only read the zero padding: a wave with none inside skips the chunk
+        if (!__any(live)) continue;
 #pragma unroll
         for (int kk = 0; kk < KC; kk++) {
 #pragma unroll
@@ -161,15 +168,16 @@ __global__ void __launch_bounds__(256)
             const long o1 = ((long)view * nv + j) * nu + i, o2 = ((long)view * nv + jm) * nu + i;
             float r1 = w * acc_t[p], r2 = w * acc_r[p];
             if (ysub) {
+                // residual mode: sum (P f - Y)^2, and hand the adjoint w * (P f - Y)
                 r1 -= ysub[o1];
                 r2 -= ysub[o2];
+                part += (double)r1 * (double)r1;
+                if (jm != j) part += (double)r2 * (double)r2;
+                r1 *= w;
+                r2 *= w;
             }
             out[o1] = r1;
-            part += (double)r1 * (double)r1;
-            if (jm != j) {
-                out[o2] = r2;
-                part += (double)r2 * (double)r2;
-            }
+            if (jm != j) out[o2] = r2;
         }
     }
     if (partials) {

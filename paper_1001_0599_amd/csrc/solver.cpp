@@ -287,7 +287,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             }
             if (last) break;
             // Step 1
-            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, s))) return st;
+            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, s, true))) return st;
             // Step 2
             if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
             // Step 3
@@ -353,7 +353,7 @@ extern "C" cbct_status cbct_tv_energy_grad(cbct_plan *p, int level, double tv_ep
                                            double *h_sum, void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
     if (!p || !d_f || !d_ws || level < 0 || level >= p->levels || !(tv_eps > 0.0))
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad: bad arguments");
-    const size_t need = align256(sizeof(double) * (CBCT_RED_BLOCKS * 3 + 8));
+    const size_t need = sizeof(double) * (CBCT_RED_BLOCKS * 3 + 8);
     if (ws_bytes < need) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad: workspace < %zu bytes", need);
     const Level &L = p->lv[level];
     hipStream_t s = (hipStream_t)stream;

@@ -36,7 +36,7 @@ class Plan:
         L = lib()
         self.geom = geom
         self.levels = int(levels)
-        self.bin_detector = bool(bin_detector)
+        self.binned = bool(bin_detector)
         self.device = torch.device("cuda", torch.cuda.current_device())
         angles = getattr(geom, "angles", None)
         self._angles = (C.c_double * len(angles))(*angles) if angles is not None else None
@@ -46,7 +46,7 @@ class Plan:
                          C.cast(self._angles, C.POINTER(C.c_double)) if self._angles is not None else None,
                          float(getattr(geom, "sample_ratio", 1.0)))
         h = C.c_void_p()
-        check(L.cbct_plan_create(C.byref(d), self.levels, int(self.bin_detector), C.byref(h)))
+        check(L.cbct_plan_create(C.byref(d), self.levels, int(self.binned), C.byref(h)))
         self._h = h
         self._dims = []
         for lvl in range(self.levels):
@@ -93,6 +93,17 @@ class Plan:
             workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
         check(lib().cbct_forward(self._h, level, f.data_ptr(), out.data_ptr(), workspace.data_ptr(),
                                  workspace.numel() * workspace.element_size(), _stream_handle(self.device)))
+        return out
+
+    def forward_columns(self, f_cols: torch.Tensor, level: int = 0, out: torch.Tensor = None):
+        """P of a volume stored [ny][nx][nz] (cbct_forward_columns)."""
+        nz, ny, nx = self.vol_shape(level)
+        _require(f_cols, (ny, nx, nz), "f_cols", self.device)
+        if out is None:
+            out = torch.empty(self.proj_shape(level), dtype=torch.float32, device=self.device)
+        _require(out, self.proj_shape(level), "out", self.device)
+        check(lib().cbct_forward_columns(self._h, level, f_cols.data_ptr(), out.data_ptr(),
+                                         _stream_handle(self.device)))
         return out
 
     def adjoint(self, y: torch.Tensor, level: int = 0, out: torch.Tensor = None):

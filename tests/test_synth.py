@@ -66,3 +66,14 @@ def test_serving_mix():
         g = r["geometry"]
         assert (g.nx, g.ny, g.nz) in ((64, 64, 64), (128, 128, 128), (256, 256, 96))
         assert 20 <= g.n_views <= 120 and g.nu == 2 * g.nx and g.nv == 2 * g.nz
+
+
+def test_torch_projections_match_numpy():
+    import torch
+    g = dataclasses.replace(S.config_geometry("cfg1"), n_views=3)
+    ph = S.make_phantom(g, 11)
+    a = S.analytic_projections(g, ph)
+    b = S.analytic_projections_torch(g, ph, "cpu").numpy()
+    assert np.max(np.abs(a - b)) < 1e-9  # rounding near tangent rays
+    y = S.poisson_log_torch(torch.as_tensor(a), 1e5, 1)
+    assert torch.isfinite(y).all()
