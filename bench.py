@@ -51,13 +51,89 @@ def cpu_baseline(g):
                       "P %.2f s, P^T %.2f s" % (t1 - t0, t2 - t1)}
 
 
+def serving_run(n_requests):
+    """The serving workload: n requests with Poisson arrivals (4/s), volumes uniform over
+    {64^3, 128^3, 256x256x96} at 2 mm, 20-120 views, detector 2Nx x 2Nz at 1.5 mm, 30 iterations,
+    200 GB budget; the continuous-admission server (8 slots) against the one-at-a-time solver
+    (1 slot) on the same arrivals, then both with all requests submitted at once (saturation)."""
+    import numpy as np
+    import torch
+
+    import cbct_synth as S
+    from paper_1001_0599_amd.serving import Server, replay, summarize
+
+    cfg = S.CONFIGS["cfg5"]
+    reqs = S.serving_requests(n_requests)
+    log("serving: synthesising %d requests on the GPU" % n_requests)
+    ys, outs = [], []
+    for r in reqs:
+        g = r["geometry"]
+        ph = S.make_phantom(g, r["phantom_seed"])
+        p = S.analytic_projections_torch(g, ph, "cuda")
+        ys.append(S.poisson_log_torch(p, cfg["I0"], r["noise_seed"]).float().contiguous())
+        outs.append(torch.empty(g.vol_shape, device="cuda"))
+    torch.cuda.synchronize()
+    arrivals = np.array([r["arrival"] for r in reqs]) - reqs[0]["arrival"]
+
+    def make(r):
+        return dict(geom=reqs[r]["geometry"], y=ys[r], out=outs[r], lam=cfg["lam"], iters=tuple(cfg["iters"]))
+
+    res = {"requests": n_requests, "budget_bytes": cfg["budget_bytes"], "iters": cfg["iters"][0]}
+    for name, slots, arr in (("served", 8, arrivals), ("plain", 1, arrivals),
+                             ("served_saturated", 8, np.zeros_like(arrivals)),
+                             ("plain_saturated", 1, np.zeros_like(arrivals))):
+        log("serving: %s (%d slots)" % (name, slots))
+        srv = Server(budget_bytes=cfg["budget_bytes"], max_slots=slots)
+        # warm the plan cache and pools with the distinct geometries is left out on purpose:
+        # first-request costs (plan tables, Schur step) are part of serving
+        lat, span, _ = replay(srv, arr, make)
+        st = srv.stats()
+        srv.close()
+        res[name] = dict(summarize(lat, span), peak_running=st["peak_running"], peak_in_use_gb=st["peak_in_use"] / 1e9)
+    return res
+
+
+def kernels_only():
+    """One launch each of a plain 256 MB copy, the projector kernel and the adjoint gather at the
+    512x512x64 / 40-view size (driver for hardware-counter runs)."""
+    import torch
+
+    import cbct_synth as S
+    from paper_1001_0599_amd.ops import Plan
+
+    torch.cuda.set_device(0)
+    g = S.config_geometry("cfg2")
+    plan = Plan(g, levels=1)
+    ph = S.make_phantom(g, 21)
+    y = S.poisson_log_torch(S.analytic_projections_torch(g, ph, "cuda"), 1e5, 22).float().contiguous()
+    f_cols = torch.rand((g.ny, g.nx, g.nz), device="cuda") * 0.02
+    proj = torch.empty_like(y)
+    vol = torch.empty(g.vol_shape, device="cuda")
+    a = torch.empty(64 * 2 ** 20, device="cuda")
+    b = torch.empty_like(a)
+    zws = torch.empty(plan.adjoint_workspace_bytes(0), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    b.copy_(a)
+    plan.forward_columns(f_cols, out=proj)
+    plan.adjoint(y, out=vol, workspace=zws)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 2 * 4 * a.numel(), "kernels": ["copy", "k_forward", "k_adj_profiles",
+                                                                    "k_adj_gather"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="also run the serving workload with N requests (256 in the full workload)")
+    ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (for counters)")
     args = ap.parse_args()
+    if args.kernels_only:
+        kernels_only()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (it times the one-GPU "
               "share of the workload); run it with --gpus 1", file=sys.stderr)
@@ -114,16 +190,17 @@ def main():
     f_cols = out.permute(1, 2, 0).contiguous()
     proj = torch.empty(plan.proj_shape(0), dtype=torch.float32, device=dev)
     vol = torch.empty(plan.vol_shape(0), dtype=torch.float32, device=dev)
+    zws = torch.empty(plan.adjoint_workspace_bytes(0), dtype=torch.uint8, device=dev)
     for _ in range(3):
         plan.forward_columns(f_cols, out=proj)
-        plan.adjoint(Y, out=vol)
+        plan.adjoint(Y, out=vol, workspace=zws)
     n_ev = 20
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n_ev)]
     for e0, e1, e2 in ev:
         e0.record()
         plan.forward_columns(f_cols, out=proj)
         e1.record()
-        plan.adjoint(Y, out=vol)
+        plan.adjoint(Y, out=vol, workspace=zws)
         e2.record()
     torch.cuda.synchronize()
     tp = float(np.mean([a.elapsed_time(b) for a, b, _ in ev])) * 1e-3
@@ -156,6 +233,8 @@ def main():
         "p_ms": tp * 1e3, "pt_ms": ta * 1e3,
         "roofline": roofline,
     }
+    if args.serving:
+        res["serving"] = serving_run(args.serving)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample)")
         res["cpu_baseline"] = cpu_baseline(g)

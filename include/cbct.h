@@ -97,10 +97,15 @@ cbct_status cbct_forward(const cbct_plan *plan, int level, const float *d_vol, f
 cbct_status cbct_forward_columns(const cbct_plan *plan, int level, const float *d_vol_cols, float *d_proj,
                                  cbct_stream_t stream);
 
+/* Workspace (device bytes) of cbct_adjoint at `level`: the z profiles of every detector
+ * column's samples (views x columns x samples in the grid's support x nz floats). */
+cbct_status cbct_adjoint_workspace_size(const cbct_plan *plan, int level, size_t *bytes);
+
 /* Adjoint P^T (exact transpose of cbct_forward; Section II.C.2): d_vol = P_level^T d_proj.
- * No workspace; the gather writes every voxel of d_vol once and uses no atomics. */
-cbct_status cbct_adjoint(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
-                         cbct_stream_t stream);
+ * d_ws: >= cbct_adjoint_workspace_size bytes, 16-byte aligned.  The voxel-driven gather writes
+ * every voxel of d_vol once and uses no atomics. */
+cbct_status cbct_adjoint(const cbct_plan *plan, int level, const float *d_proj, float *d_vol, void *d_ws,
+                         size_t ws_bytes, cbct_stream_t stream);
 
 /* ---- Reconstruction: Algorithm A1 (Section II.B) with the multigrid cascade (II.C.3) ------
  *

@@ -33,8 +33,9 @@ def _backproject(plan, y: torch.Tensor, level: int) -> torch.Tensor:
     yb, batched = _vol_batch(y, plan.proj_shape(level))
     yb = yb.contiguous()
     out = torch.empty((yb.shape[0],) + tuple(plan.vol_shape(level)), dtype=torch.float32, device=y.device)
+    ws = torch.empty(plan.adjoint_workspace_bytes(level), dtype=torch.uint8, device=y.device)
     for b in range(yb.shape[0]):
-        plan.adjoint(yb[b], level=level, out=out[b])
+        plan.adjoint(yb[b], level=level, out=out[b], workspace=ws)
     return out if batched else out[0]
 
 

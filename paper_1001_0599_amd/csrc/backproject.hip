@@ -6,19 +6,18 @@
 // are the bilinear weights of the sample's transverse position (shared by all rows of the
 // column) and Lz the linear weight of the row's z index s_kj = gamma_k q_j + (nz-1)/2.  Hence
 //   (P^T y)_abc = sum_t sum_i sum_k Lx(a) Ly(b) Z_tik(c),  Z_tik(c) = sum_j w_ij y_tji hat(s_kj - c).
-// One work-group owns a tile of 16 x 16 voxel columns and TZ z cells and keeps its sums in
-// registers across all views.  Per view, the detector columns crossing the tile are processed in
-// chunks sized to LDS; per chunk:
-//   a. the column parameters are staged in LDS, and one wave assigns a slot to every (column,
-//      sample) whose transverse position lies within one voxel of the tile;
-//   b. the weighted projections W = w y of the rows that can reach the tile are loaded with
-//      coalesced reads;
-//   c. prefix sums A[J] = sum_{J'<J} W_J', B[J] = sum_{J'<J} (J' - Jm) W_J' along each column
-//      (rows centred on the chunk's middle row Jm to limit cancellation), in 16-row blocks;
-//   d. Z of every slot at the tile's TZ cells, each in O(1) from A and B: the rows with s in
-//      [c-1, c) and [c, c+1) are the index ranges [J(c-1), J(c)) and [J(c), J(c+1)) with
-//      J(x) = ceil((x - sigma)/gamma), and the hat weights are linear in J on each range;
-//   e. each voxel column gathers Lx Ly times the slot's Z over its nearby slots.
+//
+// Two passes:
+//  1. profiles: one work-group per (view, detector column) forms FP64 prefix sums
+//     A[J] = sum_{j<J} W_j and B[J] = sum_{j<J} q_j W_j (W = w y) over the column's rows and
+//     writes Z_tik(c) for every sample k inside the grid's support and every cell c, each in O(1):
+//     the rows with s in [c-1, c) and [c, c+1) are the index ranges [J(c-1), J(c)) and
+//     [J(c), J(c+1)) with J(x) = ceil((x - (nz-1)/2)/gamma_k + (nv-1)/2), and the hat weights are
+//     linear in q_j on each range.  The profiles of a column are contiguous, cell index fastest.
+//  2. gather: a work-group owns 16 x 16 voxel columns and 16 (or 8) z cells and keeps its sums
+//     in registers across all views; per view each voxel column visits the detector columns and
+//     samples whose bilinear footprint covers it (exact windows) and adds Lx Ly times the
+//     sample's profile segment (float4 loads, shared through the caches by neighbouring voxels).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -27,65 +26,128 @@
 
 namespace {
 
-constexpr int RB = 16;  // rows per prefix-sum block
-constexpr int ZH = 8;   // cells per Z work item
-
-// q / n for 0 <= q < 2^20 and 1 <= n <= 64, via a float reciprocal with one correction step
-__device__ __forceinline__ void divmod_small(int q, int n, float inv_n, int &d, int &r) {
-    d = (int)((float)q * inv_n);
-    r = q - d * n;
-    if (r >= n) { d++; r -= n; }
-    if (r < 0) { d--; r += n; }
-}
-
-// samples k of a column whose index coordinates lie in (xa, xb) x (ya, yb), widened by one,
-// intersected with [lo, hi]
-__device__ __forceinline__ void sample_window(float fx0, float fy0, float idfx, float idfy, float xa, float xb,
-                                              float ya, float yb, float &lo, float &hi) {
-    if (idfx != 0.0f) {
-        const float ka = (xa - fx0) * idfx, kb = (xb - fx0) * idfx;
-        lo = fmaxf(lo, fminf(ka, kb) - 1.0f);
-        hi = fminf(hi, fmaxf(ka, kb) + 1.0f);
-    }
-    if (idfy != 0.0f) {
-        const float ka = (ya - fy0) * idfy, kb = (yb - fy0) * idfy;
-        lo = fmaxf(lo, fminf(ka, kb) - 1.0f);
-        hi = fminf(hi, fmaxf(ka, kb) + 1.0f);
-    }
-}
-
+// ---------------------------------------------------------------------------- pass 1
 // PREWEIGHTED: the input already holds w_ij * y (the solver's residual epilogue writes it)
-template <int TZ, bool PREWEIGHTED>
-__global__ void __launch_bounds__(256, 3)
-    k_adjoint(const float *__restrict__ proj, const ColParams *__restrict__ cols, const ViewParams *__restrict__ views,
-              AdjArgs A, const float *__restrict__ fbase, float kappa, float *__restrict__ out) {
-    constexpr int ZS = TZ + 4;  // Z row stride (floats), keeps float4 alignment
-    constexpr int NH = TZ / ZH;
-    extern __shared__ float4 lds4[];
-    const int CC = A.cc_max, RM = A.r_max, NBM = (A.r_max + RB - 1) / RB;
-    ColParams *cpl = reinterpret_cast<ColParams *>(lds4);                   // [CC]
-    int *sk0 = reinterpret_cast<int *>(cpl + CC);                           // [CC]
-    int *sn = sk0 + CC;                                                     // [CC]
-    int *sbase = sn + CC;                                                   // [CC + 1]
-    int *scol = sbase + ((CC + 1 + 3) & ~3);                                // [s_max] slot -> column
-    float2 *btot = reinterpret_cast<float2 *>(scol + ((A.s_max + 3) & ~3));  // [CC][NBM]
-    float2 *AB = btot + ((CC * NBM + 1) & ~1);                               // [CC][RM + 1]
-    float *Z = reinterpret_cast<float *>(AB + ((CC * (RM + 1) + 1) & ~1));   // [s_max][ZS]
-    const int ABS = RM + 1;
+template <bool PREWEIGHTED>
+__global__ void __launch_bounds__(256)
+    k_adj_profiles(const float *__restrict__ proj, const ColParams *__restrict__ cols,
+                   const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, float *__restrict__ Z) {
+    extern __shared__ double2 ab[];  // [nv + 1]: (A, B)
+    __shared__ double wtot[4][2];
+    const int i = blockIdx.x, view = blockIdx.y;
+    const long col = (long)view * nu + i;
+    const ColParams cp = cols[col];
+    const ZIndex zi = zix[col];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float iv = 0.5f * (float)(nv - 1);
+    // prefix sums: rows in chunks of 256, each chunk scanned by the block (wave scans + wave totals)
+    double carry_a = 0.0, carry_b = 0.0;
+    if (tid == 0) ab[0] = make_double2(0.0, 0.0);
+    for (int j0 = 0; j0 < nv; j0 += 256) {
+        const int j = j0 + tid;
+        double wa = 0.0, wb = 0.0;
+        if (j < nv) {
+            float w = proj[((long)view * nv + j) * nu + i];
+            const float q = (float)j - iv;
+            if (!PREWEIGHTED) {
+                const float v = q * pv;
+                w *= cp.wsc * sqrtf(fmaf(v, v, cp.r2));
+            }
+            wa = (double)w;
+            wb = (double)w * (double)q;
+        }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double ta = __shfl_up(wa, o), tb = __shfl_up(wb, o);
+            if (lane >= o) {
+                wa += ta;
+                wb += tb;
+            }
+        }
+        if (lane == 63) {
+            wtot[wave][0] = wa;
+            wtot[wave][1] = wb;
+        }
+        __syncthreads();
+        double oa = carry_a, ob = carry_b;
+        for (int w = 0; w < wave; w++) {
+            oa += wtot[w][0];
+            ob += wtot[w][1];
+        }
+        if (j < nv) ab[j + 1] = make_double2(oa + wa, ob + wb);
+        for (int w = 0; w < 4; w++) {
+            carry_a += wtot[w][0];
+            carry_b += wtot[w][1];
+        }
+        __syncthreads();
+    }
+    // profiles: items (sample, 4 consecutive cells), cells fastest
+    const double beta = 0.5 * (double)(nz - 1);
+    const int nq = (nz + 3) >> 2;
+    float *zc = Z + zi.off;
+    for (int it = tid; it < zi.nk * nq; it += blockDim.x) {
+        const int kk = it / nq, c4 = (it - kk * nq) << 2;
+        const double gamma = (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
+        const double ig = 1.0 / gamma;
+        int jb[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            const double x = (double)(c4 - 1 + q);
+            const double r = ceil((x - beta) * ig + (double)iv);
+            jb[q] = (int)fmin(fmax(r, 0.0), (double)nv);
+        }
+        double2 pr[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) pr[q] = ab[jb[q]];
+        float out[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const double c = (double)(c4 + q);
+            const double dal = pr[q + 1].x - pr[q].x, dbl = pr[q + 1].y - pr[q].y;          // s in [c-1, c)
+            const double dah = pr[q + 2].x - pr[q + 1].x, dbh = pr[q + 2].y - pr[q + 1].y;  // s in [c, c+1)
+            out[q] = (float)(gamma * (dbl - dbh) + (beta - c + 1.0) * dal + (c + 1.0 - beta) * dah);
+        }
+        float *dst = zc + (long)kk * nz + c4;
+        if ((nz & 3) == 0) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (c4 + q < nz) dst[q] = out[q];
+        }
+    }
+}
 
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int ta = tid % ADJ_TX, tb = tid / ADJ_TX;
-    const int a0 = blockIdx.x * ADJ_TX, b0 = blockIdx.y * ADJ_TY, c0 = blockIdx.z * TZ;
-    const int a1 = min(a0 + ADJ_TX, A.nx) - 1, b1 = min(b0 + ADJ_TY, A.ny) - 1, c1 = min(c0 + TZ, A.nz) - 1;
-    const int a = a0 + ta, b = b0 + tb;
-    const float cx = 0.5f * (float)(A.nx - 1), cy = 0.5f * (float)(A.ny - 1), cz = 0.5f * (float)(A.nz - 1);
-    const float iu = 0.5f * (float)(A.nu - 1), iv = 0.5f * (float)(A.nv - 1);
-    const float ipu = 1.0f / A.pu, ipv = 1.0f / A.pv;
-    // tile support (voxel centres +- one voxel), mm
-    const float xlo = ((float)(a0 - 1) - cx) * A.hx, xhi = ((float)(a1 + 1) - cx) * A.hx;
-    const float ylo = ((float)(b0 - 1) - cy) * A.hy, yhi = ((float)(b1 + 1) - cy) * A.hy;
-    const float zlo = ((float)(c0 - 1) - cz) * A.hz, zhi = ((float)(c1 + 1) - cz) * A.hz;
+// ---------------------------------------------------------------------------- pass 2
+// samples k of a column whose index coordinates lie in the open box (xa, xb) x (ya, yb),
+// intersected with [lo, hi]; the caller takes klo = floor(lo) + 1, khi = ceil(hi) - 1.  A sample
+// on the box boundary has interpolation weight 0 for the voxels inside.
+__device__ __forceinline__ void sample_window(const ColParams &cp, float xa, float xb, float ya, float yb, float &lo,
+                                              float &hi) {
+    if (cp.idfx != 0.0f) {
+        const float ka = (xa - cp.fx0) * cp.idfx, kb = (xb - cp.fx0) * cp.idfx;
+        lo = fmaxf(lo, fminf(ka, kb));
+        hi = fminf(hi, fmaxf(ka, kb));
+    }
+    if (cp.idfy != 0.0f) {
+        const float ka = (ya - cp.fy0) * cp.idfy, kb = (yb - cp.fy0) * cp.idfy;
+        lo = fmaxf(lo, fminf(ka, kb));
+        hi = fminf(hi, fmaxf(ka, kb));
+    }
+}
+
+template <int TZ, bool VEC>
+__global__ void __launch_bounds__(256)
+    k_adj_gather(const float *__restrict__ Z, const ZIndex *__restrict__ zix, const ColParams *__restrict__ cols,
+                 const ViewParams *__restrict__ views, AdjArgs A, const float *__restrict__ fbase, float kappa,
+                 float *__restrict__ out) {
+    const int tid = threadIdx.x;
+    const int a = blockIdx.x * ADJ_TX + tid % ADJ_TX, b = blockIdx.y * ADJ_TY + tid / ADJ_TX;
+    const int c0 = blockIdx.z * TZ;
+    const float cx = 0.5f * (float)(A.nx - 1), cy = 0.5f * (float)(A.ny - 1);
+    const float iu = 0.5f * (float)(A.nu - 1), ipu = 1.0f / A.pu;
     const float vx = ((float)a - cx) * A.hx, vy = ((float)b - cy) * A.hy;
+    if (a >= A.nx || b >= A.ny) return;
 
     float acc[TZ];
 #pragma unroll
@@ -93,230 +155,95 @@ __global__ void __launch_bounds__(256, 3)
 
     for (int view = 0; view < A.nviews; view++) {
         const ViewParams vp = views[view];
-        // detector footprint of the tile support: columns [i0, i1], rows [j0, j1]
-        float umin = FLT_MAX, umax = -FLT_MAX, vmin = FLT_MAX, vmax = -FLT_MAX;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const float x = (q & 1) ? xhi : xlo, y = (q & 2) ? yhi : ylo;
-            const float inv = A.sdd * __builtin_amdgcn_rcpf(fmaf(x, vp.cs, fmaf(y, vp.sn, A.sad)));
-            const float u = fmaf(x, vp.sn, -y * vp.cs) * inv;
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
-            vmin = fminf(vmin, fminf(zlo * inv, zhi * inv));
-            vmax = fmaxf(vmax, fmaxf(zlo * inv, zhi * inv));
-        }
-        const int i0 = max(0, (int)floorf(fmaf(umin, ipu, iu)) - 1);
-        const int i1 = min(A.nu - 1, (int)ceilf(fmaf(umax, ipu, iu)) + 1);
-        const int j0 = max(0, (int)floorf(fmaf(vmin, ipv, iv)) - 1);
-        const int j1 = min(A.nv - 1, (int)ceilf(fmaf(vmax, ipv, iv)) + 1);
-        if (i0 > i1 || j0 > j1) continue;  // the tile is outside this view's cone
-        // this voxel column's detector columns
-        float oumin = FLT_MAX, oumax = -FLT_MAX;
+        // detector columns whose samples can reach this voxel column: the footprint of its
+        // support square (centre +- one voxel), widened by one column
+        float umin = FLT_MAX, umax = -FLT_MAX;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const float x = vx + ((q & 1) ? A.hx : -A.hx), y = vy + ((q & 2) ? A.hy : -A.hy);
-            const float u = fmaf(x, vp.sn, -y * vp.cs) * A.sdd * __builtin_amdgcn_rcpf(fmaf(x, vp.cs, fmaf(y, vp.sn, A.sad)));
-            oumin = fminf(oumin, u);
-            oumax = fmaxf(oumax, u);
+            const float u = fmaf(x, vp.sn, -y * vp.cs) * A.sdd *
+                            __builtin_amdgcn_rcpf(fmaf(x, vp.cs, fmaf(y, vp.sn, A.sad)));
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
         }
-        const int oi0 = (int)floorf(fmaf(oumin, ipu, iu)) - 1, oi1 = (int)ceilf(fmaf(oumax, ipu, iu)) + 1;
-
-        for (int ci0 = i0; ci0 <= i1; ci0 += CC) {
-            const int ncol = min(CC, i1 - ci0 + 1);
-            const float inv_ncol = 1.0f / (float)ncol;
-            __syncthreads();  // the previous chunk's gather is done with LDS
-            // a. column parameters, slots and the slot -> column map (one wave; ncol <= 64)
-            if (tid < 64) {
-                int n = 0, klo = 0;
-                if (lane < ncol) {
-                    const ColParams cp = cols[(long)view * A.nu + ci0 + lane];
-                    cpl[lane] = cp;
-                    float lo = (float)cp.klo, hi = (float)cp.khi;
-                    sample_window(cp.fx0, cp.fy0, cp.idfx, cp.idfy, (float)(a0 - 1), (float)(a1 + 1), (float)(b0 - 1),
-                                  (float)(b1 + 1), lo, hi);
-                    klo = (int)ceilf(lo);
-                    n = min(max((int)floorf(hi) - klo + 1, 0), A.maxnk);
-                }
-                int incl = n;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(incl, o);
-                    if (lane >= o) incl += t;
-                }
-                const int base = incl - n;
-                if (lane < ncol) {
-                    sk0[lane] = klo;
-                    sn[lane] = n;
-                    sbase[lane] = base;
-                    for (int q = 0; q < n && base + q < A.s_max; q++) scol[base + q] = lane;
-                }
-                if (lane == ncol - 1) sbase[ncol] = min(incl, A.s_max);
-            }
-            __syncthreads();
-            const int nslots = sbase[ncol];
-
-            for (int rj0 = j0; rj0 <= j1; rj0 += RM) {
-                const int nr = min(RM, j1 - rj0 + 1);
-                const int nb = (nr + RB - 1) / RB;
-                const float rmid = (float)(nr >> 1);
-                if (rj0 != j0) __syncthreads();  // the previous row chunk's Z pass is done with AB
-                // b. weighted projections of 16-row blocks (loads coalesced along the detector row,
-                //    all in flight at once), scanned in registers
-                for (int it = tid; it < ncol * nb; it += 256) {
-                    int blk, col;
-                    divmod_small(it, ncol, inv_ncol, blk, col);
-                    const int r0 = blk * RB;
-                    const float *src = proj + ((long)view * A.nv + rj0 + r0) * A.nu + ci0 + col;
-                    float wr[RB];
-#pragma unroll
-                    for (int q = 0; q < RB; q++) wr[q] = (r0 + q < nr) ? src[(long)q * A.nu] : 0.0f;
-                    if (!PREWEIGHTED) {
-                        const float wsc = cpl[col].wsc, r2 = cpl[col].r2;
-#pragma unroll
-                        for (int q = 0; q < RB; q++) {
-                            const float v = ((float)(rj0 + r0 + q) - iv) * A.pv;
-                            wr[q] *= wsc * sqrtf(fmaf(v, v, r2));
-                        }
-                    }
-                    float2 *p = AB + col * ABS + r0 + 1;
-                    float sa = 0.0f, sbv = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < RB; q++) {
-                        sa += wr[q];
-                        sbv = fmaf(wr[q], (float)(r0 + q) - rmid, sbv);
-                        if (r0 + q < nr) p[q] = make_float2(sa, sbv);
-                    }
-                    btot[col * NBM + blk] = make_float2(sa, sbv);
-                    if (blk == 0) AB[col * ABS] = make_float2(0.0f, 0.0f);
-                }
-                __syncthreads();
-                // c. add the sums of the preceding blocks
-                for (int it = tid; it < ncol * nb; it += 256) {
-                    int blk, col;
-                    divmod_small(it, ncol, inv_ncol, blk, col);
-                    if (blk == 0) continue;
-                    float oa = 0.0f, ob = 0.0f;
-                    for (int q = 0; q < blk; q++) {
-                        const float2 t = btot[col * NBM + q];
-                        oa += t.x;
-                        ob += t.y;
-                    }
-                    const int r0 = blk * RB;
-                    float2 *p = AB + col * ABS + r0 + 1;
-#pragma unroll
-                    for (int q = 0; q < RB; q++)
-                        if (r0 + q < nr) {
-                            const float2 v = p[q];
-                            p[q] = make_float2(v.x + oa, v.y + ob);
-                        }
-                }
-                __syncthreads();
-                // d. Z of each slot at the tile's cells, ZH cells per work item
-                for (int it = tid; it < nslots * NH; it += 256) {
-                    const int sl = it / NH, h = it - sl * NH;
-                    const int t = scol[sl];
-                    const ColParams &cp = cpl[t];
-                    const int k = sk0[t] + (sl - sbase[t]);
-                    const float gamma = fmaf((float)k, cp.dg, cp.g0);
-                    const float inv_g = 1.0f / gamma;
-                    // row r of the chunk meets the column's sample at s = gamma (r - rmid) + sigma
-                    const float sigma = fmaf(gamma, (float)rj0 + rmid - iv, cz);
-                    const float2 *ab = AB + t * ABS;
-                    const int cb = c0 + h * ZH;
-                    int jb[ZH + 2];
-#pragma unroll
-                    for (int q = 0; q < ZH + 2; q++) {
-                        const float r = ceilf(fmaf((float)(cb - 1 + q) - sigma, inv_g, rmid));
-                        jb[q] = (int)fminf(fmaxf(r, 0.0f), (float)nr);
-                    }
-                    float2 pr[ZH + 2];
-#pragma unroll
-                    for (int q = 0; q < ZH + 2; q++) pr[q] = ab[jb[q]];
-                    float *zrow = Z + sl * ZS + h * ZH;
-#pragma unroll
-                    for (int q = 0; q < ZH; q++) {
-                        const float c = (float)(cb + q);
-                        const float dal = pr[q + 1].x - pr[q].x, dbl = pr[q + 1].y - pr[q].y;      // s in [c-1, c)
-                        const float dah = pr[q + 2].x - pr[q + 1].x, dbh = pr[q + 2].y - pr[q + 1].y;  // s in [c, c+1)
-                        const float zc = fmaf(gamma, dbl - dbh, fmaf(sigma - c + 1.0f, dal, (c + 1.0f - sigma) * dah));
-                        zrow[q] = (rj0 == j0) ? zc : zrow[q] + zc;
-                    }
-                }
-            }
-            __syncthreads();
-            // e. gather over this voxel column's slots
-            const int g0 = max(oi0, ci0), g1 = min(oi1, ci0 + ncol - 1);
-            for (int col = g0; col <= g1; col++) {
-                const int t = col - ci0;
-                const float fx0 = cpl[t].fx0, fy0 = cpl[t].fy0, dfx = cpl[t].dfx, dfy = cpl[t].dfy;
-                const int k0 = sk0[t], sb0 = sbase[t];
-                float lo = (float)k0, hi = (float)(k0 + sn[t] - 1);
-                sample_window(fx0, fy0, cpl[t].idfx, cpl[t].idfy, (float)(a - 1), (float)(a + 1), (float)(b - 1),
-                              (float)(b + 1), lo, hi);
-                const int klo = (int)ceilf(lo), khi = (int)floorf(hi);
-                for (int k = klo; k <= khi; k++) {
-                    const int sl = sb0 + k - k0;
-                    if (sl >= nslots) break;
-                    const float kf = (float)k;
-                    const float fx = fmaf(kf, dfx, fx0), fy = fmaf(kf, dfy, fy0);
-                    const float wxy =
-                        fmaxf(1.0f - fabsf(fx - (float)a), 0.0f) * fmaxf(1.0f - fabsf(fy - (float)b), 0.0f);
-                    if (wxy == 0.0f) continue;
-                    const float4 *zr = reinterpret_cast<const float4 *>(Z + sl * ZS);
+        const int i0 = max(0, (int)floorf(fmaf(umin, ipu, iu)) - 1);
+        const int i1 = min(A.nu - 1, (int)ceilf(fmaf(umax, ipu, iu)) + 1);
+        for (int i = i0; i <= i1; i++) {
+            const long colx = (long)view * A.nu + i;
+            const ColParams cp = cols[colx];
+            const ZIndex zi = zix[colx];
+            const float kb0 = (float)(zi.k0 - 1), kb1 = (float)(zi.k0 + zi.nk);
+            float lo = kb0, hi = kb1;
+            sample_window(cp, (float)(a - 1), (float)(a + 1), (float)(b - 1), (float)(b + 1), lo, hi);
+            // clamp before the integer conversion (near-axis columns give huge window ends), which
+            // keeps k inside [k0, k0 + nk - 1]
+            lo = fminf(fmaxf(lo, kb0), kb1);
+            hi = fminf(fmaxf(hi, kb0), kb1);
+            const int klo = (int)floorf(lo) + 1, khi = min((int)ceilf(hi) - 1, zi.k0 + zi.nk - 1);
+            for (int k = klo; k <= khi; k++) {
+                const float kf = (float)k;
+                const float fx = fmaf(kf, cp.dfx, cp.fx0), fy = fmaf(kf, cp.dfy, cp.fy0);
+                const float wxy = fmaxf(1.0f - fabsf(fx - (float)a), 0.0f) * fmaxf(1.0f - fabsf(fy - (float)b), 0.0f);
+                const float *zr = Z + zi.off + (long)(k - zi.k0) * A.nz + c0;
+                if (VEC) {
 #pragma unroll
                     for (int q = 0; q < TZ / 4; q++) {
-                        const float4 z4 = zr[q];
+                        const float4 z4 = *reinterpret_cast<const float4 *>(zr + 4 * q);
                         acc[4 * q + 0] = fmaf(wxy, z4.x, acc[4 * q + 0]);
                         acc[4 * q + 1] = fmaf(wxy, z4.y, acc[4 * q + 1]);
                         acc[4 * q + 2] = fmaf(wxy, z4.z, acc[4 * q + 2]);
                         acc[4 * q + 3] = fmaf(wxy, z4.w, acc[4 * q + 3]);
                     }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < TZ; q++)
+                        if (c0 + q < A.nz) acc[q] = fmaf(wxy, zr[q], acc[q]);
                 }
             }
         }
     }
-    if (a < A.nx && b < A.ny) {
 #pragma unroll
-        for (int q = 0; q < TZ; q++) {
-            const int c = c0 + q;
-            if (c < A.nz) {
-                const long idx = ((long)c * A.ny + b) * A.nx + a;
-                out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
-            }
+    for (int q = 0; q < TZ; q++) {
+        const int c = c0 + q;
+        if (c < A.nz) {
+            const long idx = ((long)c * A.ny + b) * A.nx + a;
+            out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
         }
     }
 }
 
-size_t adj_lds_bytes(const AdjArgs &A, int tz) {
-    const int CC = A.cc_max, NBM = (A.r_max + RB - 1) / RB;
-    size_t n = sizeof(ColParams) * CC + sizeof(int) * (3 * CC + ((CC + 1 + 3) & ~3) + ((A.s_max + 3) & ~3));
-    n = (n + 15) & ~(size_t)15;
-    n += sizeof(float2) * (((size_t)CC * NBM + 1) & ~(size_t)1);
-    n += sizeof(float2) * (((size_t)CC * (A.r_max + 1) + 1) & ~(size_t)1);
-    n += sizeof(float) * (size_t)A.s_max * (tz + 4);
-    return n + 64;
-}
+#define LAUNCH_CHECK(what)                                     \
+    do {                                                       \
+        hipError_t e_ = hipGetLastError();                     \
+        if (e_ != hipSuccess) return cbct_hip_error(e_, what); \
+    } while (0)
 
-template <int TZ, bool PW>
-cbct_status launch_adj(const Level &L, const float *proj, const float *fbase, float kappa, float *out, hipStream_t s) {
-    const size_t lds = adj_lds_bytes(L.adj, TZ);
+template <int TZ>
+cbct_status launch_gather(const Level &L, const float *Z, const float *fbase, float kappa, float *out, hipStream_t s) {
     dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (L.nz + TZ - 1) / TZ);
-    hipLaunchKernelGGL((k_adjoint<TZ, PW>), grid, dim3(ADJ_TX * ADJ_TY), lds, s, proj, L.d_cols, L.d_views, L.adj, fbase,
-                       kappa, out);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return cbct_hip_error(e, "k_adjoint launch");
+    if (L.nz % TZ == 0)
+        hipLaunchKernelGGL((k_adj_gather<TZ, true>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Z, L.d_zix, L.d_cols,
+                           L.d_views, L.adj, fbase, kappa, out);
+    else
+        hipLaunchKernelGGL((k_adj_gather<TZ, false>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Z, L.d_zix, L.d_cols,
+                           L.d_views, L.adj, fbase, kappa, out);
+    LAUNCH_CHECK("k_adj_gather");
     return CBCT_OK;
 }
 
 }  // namespace
 
-size_t cbct_adjoint_lds_bytes(const AdjArgs &A, int tz) { return adj_lds_bytes(A, tz); }
-
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
-                                hipStream_t s, bool preweighted) {
-    if (L.adj_tz == 16)
-        return preweighted ? launch_adj<16, true>(L, proj, fbase, kappa, out, s)
-                           : launch_adj<16, false>(L, proj, fbase, kappa, out, s);
-    return preweighted ? launch_adj<8, true>(L, proj, fbase, kappa, out, s)
-                       : launch_adj<8, false>(L, proj, fbase, kappa, out, s);
+                                float *Zws, hipStream_t s, bool preweighted) {
+    const size_t lds = sizeof(double2) * (L.nv + 1);
+    dim3 g1(L.nu, L.nviews);
+    if (preweighted)
+        hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
+                           (float)L.pv, Zws);
+    else
+        hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
+                           (float)L.pv, Zws);
+    LAUNCH_CHECK("k_adj_profiles");
+    if (L.nz >= 16) return launch_gather<16>(L, Zws, fbase, kappa, out, s);
+    return launch_gather<8>(L, Zws, fbase, kappa, out, s);
 }

@@ -30,17 +30,20 @@ struct ViewParams {
 // Tiling of the adjoint gather.
 constexpr int ADJ_TX = 16;     // voxel columns per tile in x (lanes)
 constexpr int ADJ_TY = 16;     // voxel columns per tile in y (lanes)
-constexpr int ADJ_MAXL = 12;   // projection loads per thread per LDS chunk (cc_max * r_max <= 256 * ADJ_MAXL)
 
-// Sizes the adjoint kernel needs per level (computed by the plan builder).
+// Geometry the adjoint gather needs per level.
 struct AdjArgs {
     int nx, ny, nz, nu, nv, nviews;
     float hx, hy, hz, pu, pv, sad, sdd;
-    int maxnk;   // max samples of one column inside one tile's support
-    int cc_max;  // detector columns per LDS chunk (<= 64)
-    int r_max;   // detector rows per LDS chunk
-    int s_max;   // slot capacity of one chunk
 };
+
+// Where the z profiles of one (view, column) live in the adjoint's workspace: samples
+// k0 .. k0+nk-1 (those whose transverse position is within one voxel of the grid), nz floats each.
+struct ZIndex {
+    long off;  // float offset, a multiple of 4
+    int k0, nk;
+};
+static_assert(sizeof(ZIndex) == 16, "ZIndex layout");
 
 struct Level {
     int nx, ny, nz, nu, nv, nviews;
@@ -50,9 +53,10 @@ struct Level {
     int fwd_pad;   // zero cells on either side of the z range in the ray-sample tables
     int fwd_kc;    // samples per table chunk
     int fwd_tw;    // table rows (z cells incl. padding)
-    // adjoint gather sizing
-    int adj_tz;    // z cells per tile
+    // adjoint
     AdjArgs adj;
+    long z_floats = 0;            // size of the profile workspace
+    ZIndex *d_zix = nullptr;      // [nviews][nu]
     double schur_t = 0.0;  // cached Schur-bound step (0: not computed yet)
     // device tables
     ColParams *d_cols = nullptr;   // [nviews][nu]
@@ -83,9 +87,9 @@ cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_
 // applied, ready for the pre-weighted adjoint) and partials[view * nu + i] = sum (P f - y_sub)^2.
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *y_sub, float *out,
                                 double *partials, hipStream_t s);
+// out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
-                                float *out, hipStream_t s, bool preweighted = false);
-size_t cbct_adjoint_lds_bytes(const AdjArgs &A, int tz);
+                                float *out, float *Zws, hipStream_t s, bool preweighted = false);
 
 // ---- solver pieces --------------------------------------------------------------------------
 constexpr int CBCT_RED_BLOCKS = 1024;  // work-groups of the fixed-size reduction grids
@@ -103,15 +107,17 @@ struct RofControl {
     int pad;
 };
 
-int cbct_reduce_blocks(long n);
+int cbct_reduce_blocks(const Level &L);
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s);
 cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, double *partials, double *sum,
                                   hipStream_t s);
+// trial energies for the M (1 or CBCT_TRIALS) step sizes t alpha^(m0 .. m0+M-1)
 cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, const float *d, const float *g,
-                                 double t, double alpha, int m0, double *partials, double *sums, hipStream_t s);
-cbct_status cbct_launch_rof_decide(const double *sums, int m0, int forced_m, long nvox, double lambda, double t,
-                                   double c_armijo, double alpha, int max_bt, RofControl *ctl, hipStream_t s);
+                                 double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s);
+cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
+                                   double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
+                                   hipStream_t s);
 cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ctl, long n, hipStream_t s);
 cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s);
 

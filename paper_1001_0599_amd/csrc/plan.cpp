@@ -62,101 +62,6 @@ static void sample_range_1d(double f0, double df, int n, double &lo, double &hi)
     hi = std::max(a, b);
 }
 
-// Sizes of the adjoint gather's LDS chunks: an FP64 replica of the kernel's per-tile column,
-// row and sample ranges (the kernel's FP32 ranges may differ by one at the margins, which the
-// capacities below absorb: the kernel also splits any range that does not fit into chunks).
-static cbct_status size_adjoint(Level &L, const std::vector<ColParams> &cols) {
-    L.adj_tz = L.nz >= 16 ? 16 : 8;
-    const int tz = L.adj_tz;
-    AdjArgs &A = L.adj;
-    A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
-    A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
-    A.sad = (float)L.sad; A.sdd = (float)L.sdd;
-    const double diag = std::sqrt(std::pow((ADJ_TX + 1) * L.hx, 2) + std::pow((ADJ_TY + 1) * L.hy, 2));
-    A.maxnk = (int)std::ceil(diag / L.dtau) + 4;
-    const double cx = 0.5 * (L.nx - 1), cy = 0.5 * (L.ny - 1), cz = 0.5 * (L.nz - 1);
-    const double iu = 0.5 * (L.nu - 1), iv = 0.5 * (L.nv - 1);
-    const int ntx = (L.nx + ADJ_TX - 1) / ADJ_TX, nty = (L.ny + ADJ_TY - 1) / ADJ_TY, ntz = (L.nz + tz - 1) / tz;
-    int max_rows = 1, max_cols = 1;
-    // per (view, xy tile): per-column slot counts; keep the max over sliding windows later
-    std::vector<std::vector<int>> counts;
-    counts.reserve((size_t)L.nviews * ntx * nty);
-    for (int v = 0; v < L.nviews; v++) {
-        const double cs = std::cos(L.angles[v]), sn = std::sin(L.angles[v]);
-        for (int ty = 0; ty < nty; ty++)
-            for (int tx = 0; tx < ntx; tx++) {
-                const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY;
-                const int a1 = std::min(a0 + ADJ_TX, L.nx) - 1, b1 = std::min(b0 + ADJ_TY, L.ny) - 1;
-                const double xl = (a0 - 1 - cx) * L.hx, xh = (a1 + 1 - cx) * L.hx;
-                const double yl = (b0 - 1 - cy) * L.hy, yh = (b1 + 1 - cy) * L.hy;
-                double umin = 1e300, umax = -1e300, dmin = 1e300, dmax = -1e300;
-                for (int q = 0; q < 4; q++) {
-                    const double x = (q & 1) ? xh : xl, y = (q & 2) ? yh : yl;
-                    const double d = x * cs + y * sn + L.sad;
-                    const double u = L.sdd * (x * sn - y * cs) / d;
-                    umin = std::min(umin, u);
-                    umax = std::max(umax, u);
-                    dmin = std::min(dmin, d);
-                    dmax = std::max(dmax, d);
-                }
-                const int i0 = std::max(0, (int)std::floor(umin / L.pu + iu) - 2);
-                const int i1 = std::min(L.nu - 1, (int)std::ceil(umax / L.pu + iu) + 2);
-                if (i0 > i1) continue;
-                max_cols = std::max(max_cols, i1 - i0 + 1);
-                for (int tzi = 0; tzi < ntz; tzi++) {
-                    const int c0 = tzi * tz, c1 = std::min(c0 + tz, L.nz) - 1;
-                    const double zl = (c0 - 1 - cz) * L.hz, zh = (c1 + 1 - cz) * L.hz;
-                    const double vmin = std::min(L.sdd * zl / dmin, L.sdd * zl / dmax);
-                    const double vmax = std::max(L.sdd * zh / dmin, L.sdd * zh / dmax);
-                    const int j0 = std::max(0, (int)std::floor(vmin / L.pv + iv) - 2);
-                    const int j1 = std::min(L.nv - 1, (int)std::ceil(vmax / L.pv + iv) + 2);
-                    if (j0 <= j1) max_rows = std::max(max_rows, j1 - j0 + 1);
-                }
-                std::vector<int> cnt(i1 - i0 + 1, 0);
-                for (int i = i0; i <= i1; i++) {
-                    const ColParams &cp = cols[(size_t)v * L.nu + i];
-                    double lo = cp.klo, hi = cp.khi;
-                    const double fx0 = cp.fx0, fy0 = cp.fy0, dfx = cp.dfx, dfy = cp.dfy;
-                    if (std::fabs(dfx) > 1e-12) {
-                        const double ka = (a0 - 1 - fx0) / dfx, kb = (a1 + 1 - fx0) / dfx;
-                        lo = std::max(lo, std::min(ka, kb) - 1.0);
-                        hi = std::min(hi, std::max(ka, kb) + 1.0);
-                    }
-                    if (std::fabs(dfy) > 1e-12) {
-                        const double ka = (b0 - 1 - fy0) / dfy, kb = (b1 + 1 - fy0) / dfy;
-                        lo = std::max(lo, std::min(ka, kb) - 1.0);
-                        hi = std::min(hi, std::max(ka, kb) + 1.0);
-                    }
-                    const int n = (int)std::floor(hi) - (int)std::ceil(lo) + 1;
-                    cnt[i - i0] = std::min(std::max(n, 0) + 2, A.maxnk);
-                }
-                counts.push_back(std::move(cnt));
-            }
-    }
-    A.r_max = std::min(max_rows + 4, 256);
-    const size_t budget = 52 * 1024;
-    for (int cc : {64, 48, 40, 32, 24, 20, 16, 12, 8, 4}) {
-        if (cc > 64) continue;
-        int smax = 0;
-        for (const auto &cnt : counts) {
-            int win = 0;
-            for (size_t q = 0; q < cnt.size(); q++) {
-                win += cnt[q];
-                if (q >= (size_t)cc) win -= cnt[q - cc];
-                smax = std::max(smax, win);
-            }
-        }
-        A.cc_max = std::min(cc, std::max(max_cols + 4, 4));
-        A.r_max = std::min(std::min(max_rows + 4, 256), (256 * ADJ_MAXL) / A.cc_max);
-        A.s_max = std::max(smax, 1);
-        if (cbct_adjoint_lds_bytes(A, tz) <= budget || cc == 4) break;
-    }
-    if (cbct_adjoint_lds_bytes(A, tz) > 64 * 1024)
-        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint tiles need %zu bytes of LDS (geometry too extreme)",
-                              cbct_adjoint_lds_bytes(A, tz));
-    return CBCT_OK;
-}
-
 static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Level &L) {
     const int f = 1 << l;
     L.nx = g->nx / f;
@@ -234,25 +139,36 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     if ((size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4 > 60 * 1024)
         return cbct_set_error(CBCT_ERR_INVALID_ARG,
                               "level %d: cone too wide for the projector tables (%d z cells)", l, L.fwd_tw);
-    // whole chunks: extend every sample range to a multiple of the chunk (the extra samples lie
-    // beyond the grid, where all interpolation weights vanish)
+    // adjoint profile workspace: the samples of each column inside the grid's support
+    std::vector<ZIndex> zix(cols.size());
+    long zoff = 0;
+    for (size_t q = 0; q < cols.size(); q++) {
+        const int nk = std::max(cols[q].khi - cols[q].klo + 1, 0);
+        zix[q] = ZIndex{zoff, cols[q].klo, nk};
+        zoff += ((long)nk * L.nz + 3) & ~3L;
+    }
+    L.z_floats = std::max(zoff, 4L);
+    AdjArgs &A = L.adj;
+    A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
+    A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
+    A.sad = (float)L.sad; A.sdd = (float)L.sdd;
+    // whole chunks for the projector: extend every sample range to a multiple of the chunk (the
+    // extra samples lie beyond the grid, where all interpolation weights vanish)
     for (auto &c : cols)
         if (c.khi >= c.klo) c.khi = c.klo + ((c.khi - c.klo + L.fwd_kc) / L.fwd_kc) * L.fwd_kc - 1;
-    // adjoint tiling
-    cbct_status sz = size_adjoint(L, cols);
-    if (sz) return sz;
 
     if (std::getenv("CBCT_PLAN_REPORT"))
         std::fprintf(stderr,
                      "[cbct plan] level %d: %dx%dx%d voxels, %d views %dx%d; fwd pad %d kc %d lds %zu; "
-                     "adj tz %d cc %d rows %d slots %d maxnk %d lds %zu\n",
+                     "adjoint profiles %.1f MB\n",
                      l, L.nx, L.ny, L.nz, L.nviews, L.nu, L.nv, L.fwd_pad, L.fwd_kc,
-                     (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4, L.adj_tz, L.adj.cc_max, L.adj.r_max, L.adj.s_max,
-                     L.adj.maxnk, cbct_adjoint_lds_bytes(L.adj, L.adj_tz));
+                     (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4, 4e-6 * (double)L.z_floats);
     CBCT_HIP(hipMalloc((void **)&L.d_cols, sizeof(ColParams) * cols.size()));
     CBCT_HIP(hipMalloc((void **)&L.d_views, sizeof(ViewParams) * views.size()));
     CBCT_HIP(hipMemcpy(L.d_cols, cols.data(), sizeof(ColParams) * cols.size(), hipMemcpyHostToDevice));
     CBCT_HIP(hipMemcpy(L.d_views, views.data(), sizeof(ViewParams) * views.size(), hipMemcpyHostToDevice));
+    CBCT_HIP(hipMalloc((void **)&L.d_zix, sizeof(ZIndex) * zix.size()));
+    CBCT_HIP(hipMemcpy(L.d_zix, zix.data(), sizeof(ZIndex) * zix.size(), hipMemcpyHostToDevice));
     return CBCT_OK;
 }
 
@@ -301,6 +217,7 @@ extern "C" void cbct_plan_destroy(cbct_plan *p) {
     for (auto &L : p->lv) {
         if (L.d_cols) hipFree(L.d_cols);
         if (L.d_views) hipFree(L.d_views);
+        if (L.d_zix) hipFree(L.d_zix);
     }
     delete p;
 }
@@ -351,12 +268,26 @@ extern "C" cbct_status cbct_forward(const cbct_plan *p, int level, const float *
     return cbct_launch_forward(L, (const float *)d_ws, nullptr, d_proj, nullptr, st);
 }
 
-extern "C" cbct_status cbct_adjoint(const cbct_plan *p, int level, const float *d_proj, float *d_vol,
-                                    cbct_stream_t stream) {
+extern "C" cbct_status cbct_adjoint_workspace_size(const cbct_plan *p, int level, size_t *bytes) {
+    cbct_status s = check_level(p, level, "adjoint_workspace_size");
+    if (s) return s;
+    if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_workspace_size: NULL out");
+    *bytes = (size_t)p->lv[level].z_floats * sizeof(float);
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_adjoint(const cbct_plan *p, int level, const float *d_proj, float *d_vol, void *d_ws,
+                                    size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "adjoint");
     if (s) return s;
-    if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: NULL pointer");
-    return cbct_launch_adjoint(p->lv[level], d_proj, nullptr, 0.0f, d_vol, (hipStream_t)stream);
+    if (!d_proj || !d_vol || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: NULL pointer");
+    const Level &L = p->lv[level];
+    if (ws_bytes < (size_t)L.z_floats * sizeof(float))
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: workspace %zu < %zu bytes", ws_bytes,
+                              (size_t)L.z_floats * sizeof(float));
+    if (((uintptr_t)d_ws & 15) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: workspace must be 16-byte aligned");
+    return cbct_launch_adjoint(L, d_proj, nullptr, 0.0f, d_vol, (float *)d_ws, (hipStream_t)stream);
 }
 
 extern "C" cbct_status cbct_forward_columns(const cbct_plan *p, int level, const float *d_vol_cols, float *d_proj,

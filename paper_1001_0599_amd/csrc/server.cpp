@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -75,6 +76,10 @@ size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<in
     size_t parts = (size_t)CBCT_RED_BLOCKS * (3 + 2 * CBCT_TRIALS);
     parts = std::max(parts, (size_t)g.n_views * g.nu);
     b += align256(8 * parts) + align256(8 * 64);
+    // adjoint profiles: at most (grid support diagonal / sample step + 3) samples per column
+    const double dtau = (g.sample_ratio > 0 ? g.sample_ratio : 1.0) * std::min(g.hx, g.hy);
+    const double diag = std::sqrt(std::pow((g.nx + 2) * g.hx, 2) + std::pow((g.ny + 2) * g.hy, 2));
+    b += align256(4 * (size_t)g.n_views * g.nu * ((size_t)std::ceil(diag / dtau) + 4) * (size_t)(g.nz + 3));
     int slots = 0;
     for (int l = 0; l < levels; l++) slots += iters[l] + 1;
     b += align256(16 * (size_t)std::max(slots, 1)) + align256(sizeof(RofControl));

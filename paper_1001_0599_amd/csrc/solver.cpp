@@ -37,7 +37,7 @@ struct Carver {
 };
 
 struct Bufs {
-    float *f, *ft, *g, *u, *d, *r;
+    float *f, *ft, *g, *u, *d, *r, *z;
     float *ypyr[8];
     double *part, *sums, *eng;
     RofControl *ctl;
@@ -60,6 +60,9 @@ Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws) {
     b.u = c.take<float>(L0.nvox());
     b.d = c.take<float>(L0.nvox());
     b.r = c.take<float>(std::max(L0.nray(), L0.nvox()));
+    long zf = 0;
+    for (int l = 0; l < levels; l++) zf = std::max(zf, p->lv[l].z_floats);
+    b.z = c.take<float>((size_t)zf);
     for (int l = 0; l < 8; l++) b.ypyr[l] = nullptr;
     for (int l = 1; l < levels; l++)
         if (p->bin_detector) b.ypyr[l] = c.take<float>(p->lv[l].nray());
@@ -108,7 +111,7 @@ cbct_status schur_step(cbct_plan *p, int level, const Bufs &b, hipStream_t s, do
     if ((st = cbct_launch_forward(L, b.ft, nullptr, b.r, nullptr, s))) return st;
     if ((st = cbct_launch_max(b.r, L.nray(), b.part, b.sums, s))) return st;
     if ((st = cbct_launch_fill(b.r, L.nray(), 1.0f, s))) return st;
-    if ((st = cbct_launch_adjoint(L, b.r, nullptr, 0.0f, b.u, s))) return st;
+    if ((st = cbct_launch_adjoint(L, b.r, nullptr, 0.0f, b.u, b.z, s))) return st;
     if ((st = cbct_launch_max(b.u, L.nvox(), b.part, b.sums + 1, s))) return st;
     double mx[2];
     CBCT_HIP(hipMemcpyAsync(mx, b.sums, sizeof(mx), hipMemcpyDeviceToHost, s));
@@ -165,11 +168,15 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
             sink.push(level, outer, it, -1, c);
             break;
         }
+        // the first window tries the full step only (it is accepted almost always); later
+        // windows try CBCT_TRIALS step sizes per pass
         int m0 = 0;
         for (;;) {
-            if ((st = cbct_launch_tv_trial(L, pr->tv_eps, b.u, b.d, b.g, t, pr->backtrack, m0, b.part, b.sums + 3, s)))
+            const int M = (m0 == 0) ? 1 : CBCT_TRIALS;
+            if ((st = cbct_launch_tv_trial(L, pr->tv_eps, b.u, b.d, b.g, t, pr->backtrack, m0, M, b.part, b.sums + 3,
+                                           s)))
                 return st;
-            if ((st = cbct_launch_rof_decide(b.sums, m0, forced >= 0 ? forced : -1, L.nvox(), pr->lambda, t,
+            if ((st = cbct_launch_rof_decide(b.sums, m0, M, forced >= 0 ? forced : -1, L.nvox(), pr->lambda, t,
                                              pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, s)))
                 return st;
             CBCT_HIP(hipMemcpyAsync(&c, b.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
@@ -287,7 +294,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             }
             if (last) break;
             // Step 1
-            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, s, true))) return st;
+            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true))) return st;
             // Step 2
             if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
             // Step 3

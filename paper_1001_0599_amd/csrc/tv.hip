@@ -70,78 +70,99 @@ __device__ __forceinline__ float phi_of(float dx, float dy, float dz, float eps2
     return sqrtf(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2))));
 }
 
+// Work distribution of the TV kernels: lanes run along x (64 per row segment), work-groups take
+// (row segment, 4 rows) tiles and stride over the (y, z) rows, so there is one division per row
+// and the grid (hence the partial-sum layout) is fixed by the shape.
+struct RowIter {
+    int nrow, row0, rstep, a0, astep;
+};
+
+__device__ __forceinline__ RowIter row_iter(const TVShape &k) {
+    RowIter it;
+    it.nrow = k.ny * k.nz;
+    it.row0 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    it.rstep = gridDim.y * 4;
+    it.a0 = blockIdx.x * 64 + (threadIdx.x & 63);
+    it.astep = gridDim.x * 64;
+    return it;
+}
+
 // d = lambda * N dR/du + (u - g)/t (g may be NULL: then d = N dR/du and lambda is ignored).
 // partials[block] = {sum phi, sum (u-g)^2, sum d^2}.
 __global__ void __launch_bounds__(256) k_tv_grad(const float *__restrict__ u, const float *__restrict__ g,
                                                  float *__restrict__ d, TVShape k, float lambda, float inv_t,
                                                  double *__restrict__ partials) {
     __shared__ double sh[4];
-    const long n = (long)k.nx * k.ny * k.nz;
     const long nxy = (long)k.nx * k.ny;
     double s_phi = 0.0, s_fid = 0.0, s_d2 = 0.0;
-    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
-        const int a = (int)(p % k.nx);
-        const int b = (int)((p / k.nx) % k.ny);
-        const int c = (int)(p / nxy);
-        float dx, dy, dz;
-        diffs(u, p, a, b, c, k, dx, dy, dz);
-        const float ph = phi_of(dx, dy, dz, k.eps2);
-        const float ip = 1.0f / ph;
-        // the z difference of the last plane is identically 0 (reflective ghost): q_z = 0 there
-        float div = -(dx * ip * k.ihx + dy * ip * k.ihy + dz * ip * k.ihz);
-        if (a >= 1) {
-            float ex, ey, ez;
-            diffs(u, p - 1, a - 1, b, c, k, ex, ey, ez);
-            div += ex / phi_of(ex, ey, ez, k.eps2) * k.ihx;
+    const RowIter ri = row_iter(k);
+    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
+        const int c = row / k.ny, b = row - c * k.ny;
+        const long rbase = (long)c * nxy + (long)b * k.nx;
+        for (int a = ri.a0; a < k.nx; a += ri.astep) {
+            const long p = rbase + a;
+            float dx, dy, dz;
+            diffs(u, p, a, b, c, k, dx, dy, dz);
+            const float ph = phi_of(dx, dy, dz, k.eps2);
+            const float ip = 1.0f / ph;
+            // the z difference of the last plane is identically 0 (reflective ghost): q_z = 0 there
+            float div = -(dx * ip * k.ihx + dy * ip * k.ihy + dz * ip * k.ihz);
+            if (a >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - 1, a - 1, b, c, k, ex, ey, ez);
+                div += ex / phi_of(ex, ey, ez, k.eps2) * k.ihx;
+            }
+            if (b >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - k.nx, a, b - 1, c, k, ex, ey, ez);
+                div += ey / phi_of(ex, ey, ez, k.eps2) * k.ihy;
+            }
+            if (c >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - nxy, a, b, c - 1, k, ex, ey, ez);
+                div += ez / phi_of(ex, ey, ez, k.eps2) * k.ihz;
+            }
+            float dv;
+            if (g) {
+                const float r = u[p] - g[p];
+                dv = fmaf(lambda, div, r * inv_t);
+                s_fid += (double)r * (double)r;
+            } else {
+                dv = div;
+            }
+            d[p] = dv;
+            s_phi += (double)ph;
+            s_d2 += (double)dv * (double)dv;
         }
-        if (b >= 1) {
-            float ex, ey, ez;
-            diffs(u, p - k.nx, a, b - 1, c, k, ex, ey, ez);
-            div += ey / phi_of(ex, ey, ez, k.eps2) * k.ihy;
-        }
-        if (c >= 1) {
-            float ex, ey, ez;
-            diffs(u, p - nxy, a, b, c - 1, k, ex, ey, ez);
-            div += ez / phi_of(ex, ey, ez, k.eps2) * k.ihz;
-        }
-        float dv;
-        if (g) {
-            const float r = u[p] - g[p];
-            dv = fmaf(lambda, div, r * inv_t);
-            s_fid += (double)r * (double)r;
-        } else {
-            dv = div;
-        }
-        d[p] = dv;
-        s_phi += (double)ph;
-        s_d2 += (double)dv * (double)dv;
     }
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     double v;
     v = block_sum(s_phi, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x * 3 + 0] = v;
+    if (threadIdx.x == 0) partials[blk * 3 + 0] = v;
     v = block_sum(s_fid, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x * 3 + 1] = v;
+    if (threadIdx.x == 0) partials[blk * 3 + 1] = v;
     v = block_sum(s_d2, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x * 3 + 2] = v;
+    if (threadIdx.x == 0) partials[blk * 3 + 2] = v;
 }
 
 // sum phi only (energy of a volume)
 __global__ void __launch_bounds__(256) k_tv_energy(const float *__restrict__ u, TVShape k,
                                                    double *__restrict__ partials) {
     __shared__ double sh[4];
-    const long n = (long)k.nx * k.ny * k.nz;
     const long nxy = (long)k.nx * k.ny;
     double s_phi = 0.0;
-    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
-        const int a = (int)(p % k.nx);
-        const int b = (int)((p / k.nx) % k.ny);
-        const int c = (int)(p / nxy);
-        float dx, dy, dz;
-        diffs(u, p, a, b, c, k, dx, dy, dz);
-        s_phi += (double)phi_of(dx, dy, dz, k.eps2);
+    const RowIter ri = row_iter(k);
+    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
+        const int c = row / k.ny, b = row - c * k.ny;
+        const long rbase = (long)c * nxy + (long)b * k.nx;
+        for (int a = ri.a0; a < k.nx; a += ri.astep) {
+            float dx, dy, dz;
+            diffs(u, rbase + a, a, b, c, k, dx, dy, dz);
+            s_phi += (double)phi_of(dx, dy, dz, k.eps2);
+        }
     }
     const double v = block_sum(s_phi, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = v;
+    if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
 // Trial energies at s_m = s0 * alpha^m, m < M.  partials[block][2m + {0,1}] = {sum phi, sum fid}.
@@ -150,7 +171,6 @@ __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, c
                                                   const float *__restrict__ g, TVShape k, double t, double alpha,
                                                   int m0, double *__restrict__ partials) {
     __shared__ double sh[4];
-    const long n = (long)k.nx * k.ny * k.nz;
     const long nxy = (long)k.nx * k.ny;
     // s_m = t alpha^(m0 + m), formed exactly as the decision kernel forms it
     float s[M];
@@ -164,26 +184,30 @@ __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, c
     double s_phi[M], s_fid[M];
 #pragma unroll
     for (int m = 0; m < M; m++) s_phi[m] = s_fid[m] = 0.0;
-    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
-        const int a = (int)(p % k.nx);
-        const int b = (int)((p / k.nx) % k.ny);
-        const int c = (int)(p / nxy);
-        const float gp = g[p];
+    const RowIter ri = row_iter(k);
+    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
+        const int c = row / k.ny, b = row - c * k.ny;
+        const long rbase = (long)c * nxy + (long)b * k.nx;
+        for (int a = ri.a0; a < k.nx; a += ri.astep) {
+            const long p = rbase + a;
+            const float gp = g[p];
 #pragma unroll
-        for (int m = 0; m < M; m++) {
-            float w0, dx, dy, dz;
-            diffs_step(u, d, s[m], p, a, b, c, k, w0, dx, dy, dz);
-            const float r = w0 - gp;
-            s_phi[m] += (double)phi_of(dx, dy, dz, k.eps2);
-            s_fid[m] += (double)r * (double)r;
+            for (int m = 0; m < M; m++) {
+                float w0, dx, dy, dz;
+                diffs_step(u, d, s[m], p, a, b, c, k, w0, dx, dy, dz);
+                const float r = w0 - gp;
+                s_phi[m] += (double)phi_of(dx, dy, dz, k.eps2);
+                s_fid[m] += (double)r * (double)r;
+            }
         }
     }
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int m = 0; m < M; m++) {
         double v = block_sum(s_phi[m], sh);
-        if (threadIdx.x == 0) partials[blockIdx.x * 2 * M + 2 * m] = v;
+        if (threadIdx.x == 0) partials[blk * 2 * M + 2 * m] = v;
         v = block_sum(s_fid[m], sh);
-        if (threadIdx.x == 0) partials[blockIdx.x * 2 * M + 2 * m + 1] = v;
+        if (threadIdx.x == 0) partials[blk * 2 * M + 2 * m + 1] = v;
     }
 }
 
@@ -255,9 +279,18 @@ static TVShape tv_shape(const Level &L, double eps) {
                    (float)(eps * eps)};
 }
 
-int cbct_reduce_blocks(long n) {
-    long b = (n + 255) / 256;
-    return (int)std::min<long>(std::max<long>(b, 1), CBCT_RED_BLOCKS);
+// fixed reduction grid of a volume: (x segments of 64) x (row groups of 4), about
+// CBCT_RED_BLOCKS work-groups
+static dim3 tv_grid(const Level &L) {
+    const int gx = (L.nx + 63) / 64;
+    const int rows = (L.ny * L.nz + 3) / 4;
+    const int gy = std::max(1, std::min(rows, CBCT_RED_BLOCKS / gx));
+    return dim3(gx, gy);
+}
+
+int cbct_reduce_blocks(const Level &L) {
+    const dim3 g = tv_grid(L);
+    return (int)(g.x * g.y);
 }
 
 #define LAUNCH_CHECK(what)                                  \
@@ -268,8 +301,8 @@ int cbct_reduce_blocks(long n) {
 
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L.nvox());
-    hipLaunchKernelGGL(k_tv_grad, dim3(nb), dim3(256), 0, s, u, g, d, tv_shape(L, eps), (float)lambda,
+    const int nb = cbct_reduce_blocks(L);
+    hipLaunchKernelGGL(k_tv_grad, tv_grid(L), dim3(256), 0, s, u, g, d, tv_shape(L, eps), (float)lambda,
                        (float)(1.0 / t), partials);
     LAUNCH_CHECK("k_tv_grad");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 3, sums);
@@ -279,8 +312,8 @@ cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, cons
 
 cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, double *partials, double *sum,
                                   hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L.nvox());
-    hipLaunchKernelGGL(k_tv_energy, dim3(nb), dim3(256), 0, s, u, tv_shape(L, eps), partials);
+    const int nb = cbct_reduce_blocks(L);
+    hipLaunchKernelGGL(k_tv_energy, tv_grid(L), dim3(256), 0, s, u, tv_shape(L, eps), partials);
     LAUNCH_CHECK("k_tv_energy");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 1, sum);
     LAUNCH_CHECK("k_sum_rows");
@@ -288,20 +321,25 @@ cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, do
 }
 
 cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, const float *d, const float *g,
-                                 double t, double alpha, int m0, double *partials, double *sums, hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L.nvox());
-    hipLaunchKernelGGL((k_tv_trial<CBCT_TRIALS>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha,
-                       m0, partials);
+                                 double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s) {
+    const int nb = cbct_reduce_blocks(L);
+    if (M == 1)
+        hipLaunchKernelGGL((k_tv_trial<1>), tv_grid(L), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha, m0,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_tv_trial<CBCT_TRIALS>), tv_grid(L), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t,
+                           alpha, m0, partials);
     LAUNCH_CHECK("k_tv_trial");
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 2 * CBCT_TRIALS, sums);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 2 * (M == 1 ? 1 : CBCT_TRIALS), sums);
     LAUNCH_CHECK("k_sum_rows");
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_rof_decide(const double *sums, int m0, int forced_m, long nvox, double lambda, double t,
-                                   double c_armijo, double alpha, int max_bt, RofControl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_rof_decide, dim3(1), dim3(64), 0, s, sums, CBCT_TRIALS, m0, forced_m, 1.0 / (double)nvox,
-                       lambda, t, c_armijo, alpha, max_bt, ctl);
+cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
+                                   double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_rof_decide, dim3(1), dim3(64), 0, s, sums, M, m0, forced_m, 1.0 / (double)nvox, lambda, t,
+                       c_armijo, alpha, max_bt, ctl);
     LAUNCH_CHECK("k_rof_decide");
     return CBCT_OK;
 }

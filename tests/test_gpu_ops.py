@@ -140,4 +140,4 @@ def test_input_validation():
     L = _lib.lib()
     assert L.cbct_forward(plan.handle, 1, x.data_ptr(), y.data_ptr(), x.data_ptr(), 4 * x.numel(), None) == 1
     assert L.cbct_forward(plan.handle, 0, x.data_ptr(), y.data_ptr(), x.data_ptr(), 16, None) == 1
-    assert L.cbct_adjoint(plan.handle, -1, y.data_ptr(), x.data_ptr(), None) == 1
+    assert L.cbct_adjoint(plan.handle, -1, y.data_ptr(), x.data_ptr(), None, 0, None) == 1

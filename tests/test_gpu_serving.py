@@ -55,8 +55,10 @@ def test_mixed_requests_equal_solo_results():
 def test_budget_serialises_when_tight():
     from paper_1001_0599_amd.serving import Server
     reqs = _requests()[:3]
+    # one slot: the peak is the largest single request
     srv = Server(budget_bytes=1e12, max_slots=1)
-    srv.submit(reqs[0][0], reqs[0][1], torch.empty(reqs[0][0].vol_shape, device="cuda"), iters=(2,))
+    for g, y in reqs:
+        srv.submit(g, y, torch.empty(g.vol_shape, device="cuda"), iters=(2,))
     srv.wait_all()
     one = srv.stats()["peak_in_use"]
     srv.close()
