@@ -25,6 +25,38 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the P^T operator per launch, from hardware counters (FETCH_SIZE and WRITE_SIZE,
+# each scaled by what the counter reads for a plain copy of known size).  The record names the
+# sources it was measured on; it is reported only while they are unchanged.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "adjoint_traffic_512x512x64_40views.txt")
+TRAFFIC_SOURCES = ["backproject.hip", "cbct_internal.h", "plan.cpp"]
+
+
+def sources_digest(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1001_0599_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter record, or None if it is missing or stale."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != sources_digest(TRAFFIC_SOURCES):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(g):
     """The FP64 oracle on the host cores, on a bounded sample of the workload: P and P^T of 12 of
     the 40 views (every ray of those views, the full volume), scaled to voxel*views/s."""
@@ -118,7 +150,7 @@ def kernels_only():
     plan.adjoint(y, out=vol, workspace=zws)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": 2 * 4 * a.numel(), "kernels": ["copy", "k_forward", "k_adj_profiles",
-                                                                    "k_adj_gather"]}))
+                                                                    "k_adj_gather_staged"]}))
 
 
 def main():
@@ -209,10 +241,14 @@ def main():
     # algorithmic bytes per launch: the volume read (P) or written (P^T) once per view, plus the
     # detector samples in and out (4 B each)
     alg_bytes = 4.0 * vv + 8.0 * g.n_views * g.nu * g.nv
-    dom, t_dom = ("k_adjoint", ta) if ta >= tp else ("k_forward", tp)
+    # the dominant operator: P^T (two launches, z profiles then the gather) or P (one launch)
+    if ta >= tp:
+        dom, t_dom, traffic = "P^T: k_adj_profiles + k_adj_gather_staged", ta, measured_traffic()
+    else:
+        dom, t_dom, traffic = "P: k_forward", tp, None
     achieved = alg_bytes / t_dom / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                 "kernel_ms": t_dom * 1e3, "bytes_per_launch": alg_bytes}
 
     res = {

@@ -174,9 +174,12 @@ cbct_status cbct_tv_prox_workspace_size(const cbct_plan *plan, int level, size_t
 cbct_status cbct_tv_prox(cbct_plan *plan, int level, const cbct_solve_params *params, const float *d_g,
                          float *d_u, void *d_ws, size_t ws_bytes, cbct_stream_t stream, cbct_solve_stats *stats);
 
+/* Workspace (device bytes) of cbct_tv_energy_grad (fixed-order partial sums). */
+cbct_status cbct_tv_energy_grad_workspace_size(const cbct_plan *plan, size_t *bytes);
+
 /* Smoothed TV sum S(f) = sum_voxels sqrt(|D f|^2 + tv_eps^2) (= N_vox R(f)) and its gradient
  * dS/df into d_grad (may be NULL).  h_sum may be NULL; if not, the call synchronises `stream`
- * and writes S.  d_ws: >= 8 * (3 * 1024 + 8) bytes. */
+ * and writes S.  d_ws: >= cbct_tv_energy_grad_workspace_size bytes, 8-byte aligned. */
 cbct_status cbct_tv_energy_grad(cbct_plan *plan, int level, double tv_eps, const float *d_f, float *d_grad,
                                 double *h_sum, void *d_ws, size_t ws_bytes, cbct_stream_t stream);
 

@@ -67,6 +67,7 @@ _SIG = [
     ("cbct_tv_prox_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
     ("cbct_tv_prox", C.c_int, [_VP, C.c_int, C.POINTER(SolveParams), _VP, _VP, _VP, C.c_size_t, _VP,
                                C.POINTER(SolveStats)]),
+    ("cbct_tv_energy_grad_workspace_size", C.c_int, [_VP, C.POINTER(C.c_size_t)]),
     ("cbct_tv_energy_grad", C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, C.POINTER(C.c_double), _VP, C.c_size_t,
                                       _VP]),
     ("cbct_prolong", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),

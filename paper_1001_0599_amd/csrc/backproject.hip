@@ -14,7 +14,7 @@
 //     the rows with s in [c-1, c) and [c, c+1) are the index ranges [J(c-1), J(c)) and
 //     [J(c), J(c+1)) with J(x) = ceil((x - (nz-1)/2)/gamma_k + (nv-1)/2), and the hat weights are
 //     linear in q_j on each range.  The profiles of a column are contiguous, cell index fastest.
-//  2. gather: a work-group owns 16 x 16 voxel columns and 16 (or 8) z cells and keeps its sums
+//  2. gather: a work-group owns 16 x 16 voxel columns and up to 64 z cells and keeps its sums
 //     in registers across all views; per view each voxel column visits the detector columns and
 //     samples whose bilinear footprint covers it (exact windows) and adds Lx Ly times the
 //     sample's profile segment (float4 loads, shared through the caches by neighbouring voxels).
@@ -34,7 +34,9 @@ __global__ void __launch_bounds__(256)
                    const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, float *__restrict__ Z) {
     extern __shared__ double2 ab[];  // [nv + 1]: (A, B)
     __shared__ double wtot[4][2];
-    const int i = blockIdx.x, view = blockIdx.y;
+    // adjacent columns share the cache lines of their projection rows: keep them on one XCD
+    const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int i = w % nu, view = w / nu;
     const long col = (long)view * nu + i;
     const ColParams cp = cols[col];
     const ZIndex zi = zix[col];
@@ -81,39 +83,45 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
     }
-    // profiles: items (sample, 4 consecutive cells), cells fastest
+    // profiles: items (sample, CG consecutive cells), cells fastest.  J(x) = ceil(x / gamma + iv -
+    // beta / gamma) is monotone in x, so the row ranges [J(c-1), J(c)) and [J(c), J(c+1)) never
+    // overlap; CG + 2 boundaries serve the item's CG cells.
+#ifndef CBCT_PROF_CG
+#define CBCT_PROF_CG 4
+#endif
+    constexpr int CG = CBCT_PROF_CG;
     const double beta = 0.5 * (double)(nz - 1);
-    const int nq = (nz + 3) >> 2;
+    const int nq = (nz + CG - 1) / CG;
+    const bool vec = (nz & 3) == 0;
     float *zc = Z + zi.off;
     for (int it = tid; it < zi.nk * nq; it += blockDim.x) {
-        const int kk = it / nq, c4 = (it - kk * nq) << 2;
+        const int kk = it / nq, cg0 = (it - kk * nq) * CG;
         const double gamma = (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
         const double ig = 1.0 / gamma;
-        int jb[6];
+        const double base = (double)iv - beta * ig;
+        double2 pr[CG + 2];
 #pragma unroll
-        for (int q = 0; q < 6; q++) {
-            const double x = (double)(c4 - 1 + q);
-            const double r = ceil((x - beta) * ig + (double)iv);
-            jb[q] = (int)fmin(fmax(r, 0.0), (double)nv);
+        for (int q = 0; q < CG + 2; q++) {
+            const double r = ceil(fma((double)(cg0 - 1 + q), ig, base));
+            pr[q] = ab[(int)fmin(fmax(r, 0.0), (double)nv)];
         }
-        double2 pr[6];
+        float o[CG];
 #pragma unroll
-        for (int q = 0; q < 6; q++) pr[q] = ab[jb[q]];
-        float out[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const double c = (double)(c4 + q);
+        for (int q = 0; q < CG; q++) {
+            const double c = (double)(cg0 + q);
             const double dal = pr[q + 1].x - pr[q].x, dbl = pr[q + 1].y - pr[q].y;          // s in [c-1, c)
             const double dah = pr[q + 2].x - pr[q + 1].x, dbh = pr[q + 2].y - pr[q + 1].y;  // s in [c, c+1)
-            out[q] = (float)(gamma * (dbl - dbh) + (beta - c + 1.0) * dal + (c + 1.0 - beta) * dah);
+            o[q] = (float)(gamma * (dbl - dbh) + (beta - c + 1.0) * dal + (c + 1.0 - beta) * dah);
         }
-        float *dst = zc + (long)kk * nz + c4;
-        if ((nz & 3) == 0) {
-            *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[3]);
+        float *dst = zc + (long)kk * nz + cg0;
+        if (vec && (CG & 3) == 0 && cg0 + CG <= nz) {
+#pragma unroll
+            for (int q = 0; q < CG / 4; q++)
+                *reinterpret_cast<float4 *>(dst + 4 * q) = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; q++)
-                if (c4 + q < nz) dst[q] = out[q];
+            for (int q = 0; q < CG; q++)
+                if (cg0 + q < nz) dst[q] = o[q];
         }
     }
 }
@@ -122,18 +130,52 @@ __global__ void __launch_bounds__(256)
 // samples k of a column whose index coordinates lie in the open box (xa, xb) x (ya, yb),
 // intersected with [lo, hi]; the caller takes klo = floor(lo) + 1, khi = ceil(hi) - 1.  A sample
 // on the box boundary has interpolation weight 0 for the voxels inside.
+__device__ __forceinline__ void window4(float fx0, float idfx, float fy0, float idfy, float xa, float xb, float ya,
+                                        float yb, float &lo, float &hi) {
+    if (idfx != 0.0f) {
+        const float ka = (xa - fx0) * idfx, kb = (xb - fx0) * idfx;
+        lo = fmaxf(lo, fminf(ka, kb));
+        hi = fminf(hi, fmaxf(ka, kb));
+    }
+    if (idfy != 0.0f) {
+        const float ka = (ya - fy0) * idfy, kb = (yb - fy0) * idfy;
+        lo = fmaxf(lo, fminf(ka, kb));
+        hi = fminf(hi, fmaxf(ka, kb));
+    }
+}
+
 __device__ __forceinline__ void sample_window(const ColParams &cp, float xa, float xb, float ya, float yb, float &lo,
                                               float &hi) {
-    if (cp.idfx != 0.0f) {
-        const float ka = (xa - cp.fx0) * cp.idfx, kb = (xb - cp.fx0) * cp.idfx;
-        lo = fmaxf(lo, fminf(ka, kb));
-        hi = fminf(hi, fmaxf(ka, kb));
+    window4(cp.fx0, cp.idfx, cp.fy0, cp.idfy, xa, xb, ya, yb, lo, hi);
+}
+
+// detector columns [i0, i1] whose rays cross the box [xa, xb] x [ya, yb] (mm, centred
+// coordinates), widened by `widen` columns on each side: the central projections of the corners
+// bound those of the whole box
+__device__ __forceinline__ void box_columns(const AdjArgs &A, const ViewParams &vp, float xa, float xb, float ya,
+                                            float yb, int widen, int &i0, int &i1) {
+    float umin = FLT_MAX, umax = -FLT_MAX;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const float x = (q & 1) ? xb : xa, y = (q & 2) ? yb : ya;
+        const float u = fmaf(x, vp.sn, -y * vp.cs) * A.sdd * __builtin_amdgcn_rcpf(fmaf(x, vp.cs, fmaf(y, vp.sn, A.sad)));
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
     }
-    if (cp.idfy != 0.0f) {
-        const float ka = (ya - cp.fy0) * cp.idfy, kb = (yb - cp.fy0) * cp.idfy;
-        lo = fmaxf(lo, fminf(ka, kb));
-        hi = fminf(hi, fmaxf(ka, kb));
-    }
+    const float iu = 0.5f * (float)(A.nu - 1), ipu = 1.0f / A.pu;
+    i0 = max(0, (int)ceilf(fmaf(umin, ipu, iu)) - widen);
+    i1 = min(A.nu - 1, (int)floorf(fmaf(umax, ipu, iu)) + widen);
+}
+
+// Work-group -> tile: each XCD gets a contiguous band of tiles, whose neighbouring voxel
+// columns read the same profiles through that XCD's L2.
+__device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    int w = cbct_xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    tx = w % gx;
+    w /= gx;
+    ty = w % gy;
+    tz = w / gy;
 }
 
 template <int TZ, bool VEC>
@@ -141,9 +183,11 @@ __global__ void __launch_bounds__(256)
     k_adj_gather(const float *__restrict__ Z, const ZIndex *__restrict__ zix, const ColParams *__restrict__ cols,
                  const ViewParams *__restrict__ views, AdjArgs A, const float *__restrict__ fbase, float kappa,
                  float *__restrict__ out) {
+    int tx, ty, tz;
+    tile_of(tx, ty, tz);
     const int tid = threadIdx.x;
-    const int a = blockIdx.x * ADJ_TX + tid % ADJ_TX, b = blockIdx.y * ADJ_TY + tid / ADJ_TX;
-    const int c0 = blockIdx.z * TZ;
+    const int a = tx * ADJ_TX + tid % ADJ_TX, b = ty * ADJ_TY + tid / ADJ_TX;
+    const int c0 = tz * TZ;
     const float cx = 0.5f * (float)(A.nx - 1), cy = 0.5f * (float)(A.ny - 1);
     const float iu = 0.5f * (float)(A.nu - 1), ipu = 1.0f / A.pu;
     const float vx = ((float)a - cx) * A.hx, vy = ((float)b - cy) * A.hy;
@@ -212,6 +256,183 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ---------------------------------------------------------------------------- pass 2, staged
+// For nz a multiple of 32: a work-group owns 16 x 16 voxel columns x 32 z cells (one 128-byte
+// line of every profile row).  Per view it lists the detector columns crossing its box and the
+// samples of each inside the box (+ one voxel), stages those profile rows in LDS with coalesced
+// loads (8 lanes per row), and every voxel column then gathers its hits from LDS.  Each profile
+// line is read from L2 once per tile and view instead of once per voxel that uses it.
+#ifndef CBCT_GS_ROWS
+#define CBCT_GS_ROWS 224
+#endif
+constexpr int GS_TZ = 32;              // z cells per tile
+constexpr int GS_ROWS = CBCT_GS_ROWS;  // staged rows per batch
+constexpr int GS_CC = 64;              // detector columns per column chunk (one wave lists them)
+constexpr int GS_PITCH = GS_TZ / 4 + 1;  // float4 slots per staged row (one pad slot against bank conflicts)
+
+struct GsCol {
+    float fx0, dfx, fy0, dfy, idfx, idfy;
+    int ka, kb;  // samples of the column inside the tile box
+    long zrow;   // float offset of sample ka's cells c0.. in the profiles
+};
+
+// With view groups (vgroups > 1) the work-group of group g covers views [g vper, (g+1) vper) and
+// writes its sums to part[g]; k_adj_combine adds the groups in order.
+__global__ void __launch_bounds__(256)
+    k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
+                        const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
+                        int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
+                        float *__restrict__ part) {
+    __shared__ float4 zs[GS_ROWS * GS_PITCH];
+    __shared__ GsCol ci[GS_CC];
+    __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
+    __shared__ long rowsrc[GS_ROWS];  // profile offset of each staged row
+
+    int tx, ty, tzg;
+    tile_of(tx, ty, tzg);
+    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = tzg / nzt;
+    const int v_begin = grp * vper, v_end = min(A.nviews, v_begin + vper);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY, c0 = tz * GS_TZ;
+    const int a = a0 + (tid & (ADJ_TX - 1)), b = b0 + tid / ADJ_TX;
+    const bool inside = a < A.nx && b < A.ny;
+    const int alast = min(a0 + ADJ_TX - 1, A.nx - 1), blast = min(b0 + ADJ_TY - 1, A.ny - 1);
+    const float cx = 0.5f * (float)(A.nx - 1), cy = 0.5f * (float)(A.ny - 1);
+    // supports in mm: the tile's (union of the voxels' centre +- one voxel) and this voxel's
+    const float txa = ((float)(a0 - 1) - cx) * A.hx, txb = ((float)(alast + 1) - cx) * A.hx;
+    const float tya = ((float)(b0 - 1) - cy) * A.hy, tyb = ((float)(blast + 1) - cy) * A.hy;
+    const float vxa = ((float)(a - 1) - cx) * A.hx, vxb = ((float)(a + 1) - cx) * A.hx;
+    const float vya = ((float)(b - 1) - cy) * A.hy, vyb = ((float)(b + 1) - cy) * A.hy;
+
+    float acc[GS_TZ];
+#pragma unroll
+    for (int q = 0; q < GS_TZ; q++) acc[q] = 0.0f;
+
+    for (int view = v_begin; view < v_end; view++) {
+        const ViewParams vp = views[view];
+        int I0, I1, i0, i1;
+        // the tile's list is widened so that it holds every column a voxel of the tile visits
+        // (the voxel's exact range may round differently); a column whose ray only grazes a
+        // support's edge carries weights of rounding size either way
+        box_columns(A, vp, txa, txb, tya, tyb, 2, I0, I1);
+        box_columns(A, vp, vxa, vxb, vya, vyb, 0, i0, i1);
+        for (int cb = I0; cb <= I1; cb += GS_CC) {
+            const int nc = min(GS_CC, I1 - cb + 1);
+            // list the chunk's columns and their samples inside the tile box
+            if (wave == 0) {
+                int nr = 0;
+                if (lane < nc) {
+                    const long colx = (long)view * A.nu + cb + lane;
+                    const ColParams cp = cols[colx];
+                    const ZIndex zi = zix[colx];
+                    const float kb0 = (float)(zi.k0 - 1), kb1 = (float)(zi.k0 + zi.nk);
+                    float lo = kb0, hi = kb1;
+                    sample_window(cp, (float)(a0 - 1), (float)(alast + 1), (float)(b0 - 1), (float)(blast + 1), lo,
+                                  hi);
+                    lo = fminf(fmaxf(lo, kb0), kb1);
+                    hi = fminf(fmaxf(hi, kb0), kb1);
+                    const int ka = (int)floorf(lo) + 1, kb = min((int)ceilf(hi) - 1, zi.k0 + zi.nk - 1);
+                    nr = max(kb - ka + 1, 0);
+                    GsCol g;
+                    g.fx0 = cp.fx0;
+                    g.dfx = cp.dfx;
+                    g.fy0 = cp.fy0;
+                    g.dfy = cp.dfy;
+                    g.idfx = cp.idfx;
+                    g.idfy = cp.idfy;
+                    g.ka = ka;
+                    g.kb = ka + nr - 1;
+                    g.zrow = zi.off + (long)(ka - zi.k0) * A.nz + c0;
+                    ci[lane] = g;
+                }
+                int incl = nr;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o);
+                    if (lane >= o) incl += t;
+                }
+                if (lane < nc) cnt[lane + 1] = incl;
+                if (lane == 0) cnt[0] = 0;
+            }
+            __syncthreads();
+            const int total = cnt[nc];
+            // this voxel column's columns within the chunk
+            const int t_lo = max(i0 - cb, 0), t_hi = min(i1 - cb, nc - 1);
+            for (int R0 = 0; R0 < total; R0 += GS_ROWS) {
+                const int nrows = min(GS_ROWS, total - R0);
+                // profile offsets of this batch's rows
+                if (tid < nc) {
+                    const int r_a = max(cnt[tid], R0), r_b = min(cnt[tid + 1], R0 + nrows);
+                    const long z0 = ci[tid].zrow - (long)cnt[tid] * A.nz;
+                    for (int r = r_a; r < r_b; r++) rowsrc[r - R0] = z0 + (long)r * A.nz;
+                }
+                __syncthreads();
+                // stage the rows: 8 lanes per 128-byte row
+                for (int it = tid; it < nrows * (GS_TZ / 4); it += blockDim.x) {
+                    const int r = it >> 3, q = it & 7;
+                    zs[r * GS_PITCH + q] = *reinterpret_cast<const float4 *>(Z + rowsrc[r] + 4 * q);
+                }
+                __syncthreads();
+                if (inside) {
+                    for (int t = t_lo; t <= t_hi; t++) {
+                        const GsCol g = ci[t];
+                        // staged samples of column t in this batch
+                        const int kfirst = max(g.ka, g.ka + R0 - cnt[t]);
+                        const int klast = min(g.kb, g.ka + R0 + nrows - 1 - cnt[t]);
+                        const float kb0 = (float)(kfirst - 1), kb1 = (float)(klast + 1);
+                        float lo = kb0, hi = kb1;
+                        window4(g.fx0, g.idfx, g.fy0, g.idfy, (float)(a - 1), (float)(a + 1), (float)(b - 1),
+                                (float)(b + 1), lo, hi);
+                        lo = fminf(fmaxf(lo, kb0), kb1);
+                        hi = fminf(fmaxf(hi, kb0), kb1);
+                        const int klo = (int)floorf(lo) + 1, khi = min((int)ceilf(hi) - 1, klast);
+                        const int rbase = cnt[t] - R0 - g.ka;  // staged row of sample k: rbase + k
+                        for (int k = klo; k <= khi; k++) {
+                            const float kf = (float)k;
+                            const float fx = fmaf(kf, g.dfx, g.fx0), fy = fmaf(kf, g.dfy, g.fy0);
+                            const float wxy =
+                                fmaxf(1.0f - fabsf(fx - (float)a), 0.0f) * fmaxf(1.0f - fabsf(fy - (float)b), 0.0f);
+                            const float4 *zr = zs + (rbase + k) * GS_PITCH;
+#pragma unroll
+                            for (int q = 0; q < GS_TZ / 4; q++) {
+                                const float4 z4 = zr[q];
+                                acc[4 * q + 0] = fmaf(wxy, z4.x, acc[4 * q + 0]);
+                                acc[4 * q + 1] = fmaf(wxy, z4.y, acc[4 * q + 1]);
+                                acc[4 * q + 2] = fmaf(wxy, z4.z, acc[4 * q + 2]);
+                                acc[4 * q + 3] = fmaf(wxy, z4.w, acc[4 * q + 3]);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            // every wave has read this chunk's list before the next chunk overwrites it (also when
+            // it had no rows, so no batch barrier ran)
+            __syncthreads();
+        }
+    }
+    if (inside) {
+        const long nvox = (long)A.nx * A.ny * A.nz;
+#pragma unroll
+        for (int q = 0; q < GS_TZ; q++) {
+            const long idx = ((long)(c0 + q) * A.ny + b) * A.nx + a;
+            if (vgroups > 1) part[grp * nvox + idx] = acc[q];
+            else out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
+        }
+    }
+}
+
+// out = sum of the view groups' partial volumes (in group order), or fbase - kappa * that sum
+__global__ void __launch_bounds__(256) k_adj_combine(const float *__restrict__ part, int vgroups, long n,
+                                                     const float *__restrict__ fbase, float kappa,
+                                                     float *__restrict__ out) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        float s = part[i];
+        for (int g = 1; g < vgroups; g++) s += part[g * n + i];
+        out[i] = fbase ? fmaf(-kappa, s, fbase[i]) : s;
+    }
+}
+
 #define LAUNCH_CHECK(what)                                     \
     do {                                                       \
         hipError_t e_ = hipGetLastError();                     \
@@ -244,6 +465,34 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
         hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
                            (float)L.pv, Zws);
     LAUNCH_CHECK("k_adj_profiles");
-    if (L.nz >= 16) return launch_gather<16>(L, Zws, fbase, kappa, out, s);
-    return launch_gather<8>(L, Zws, fbase, kappa, out, s);
+    const int nz = L.nz;
+    if (nz % GS_TZ == 0) {
+        const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
+        float *part = Zws + L.adj_part_off;
+        dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / GS_TZ) * vg);
+        hipLaunchKernelGGL(k_adj_gather_staged, grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix, L.d_cols, L.d_views,
+                           L.adj, vg, vper, fbase, kappa, out, part);
+        LAUNCH_CHECK("k_adj_gather_staged");
+        if (vg > 1) {
+            const long n = L.nvox();
+            const int nb = (int)std::min<long>((n + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out);
+            LAUNCH_CHECK("k_adj_combine");
+        }
+        return CBCT_OK;
+    }
+    // other depths: per-lane gather, z cells per thread up to 64 (the window and weight work per
+    // voxel column and view is shared by all its cells)
+    int tz;
+    if (nz % 64 == 0) tz = 64;
+    else if (nz % 32 == 0) tz = 32;
+    else if (nz % 16 == 0) tz = 16;
+    else if (nz % 8 == 0) tz = 8;
+    else tz = nz > 32 ? 64 : nz > 16 ? 32 : nz > 8 ? 16 : 8;  // partial last tile, scalar loads
+    switch (tz) {
+        case 64: return launch_gather<64>(L, Zws, fbase, kappa, out, s);
+        case 32: return launch_gather<32>(L, Zws, fbase, kappa, out, s);
+        case 16: return launch_gather<16>(L, Zws, fbase, kappa, out, s);
+        default: return launch_gather<8>(L, Zws, fbase, kappa, out, s);
+    }
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -37,10 +38,21 @@ struct AdjArgs {
     float hx, hy, hz, pu, pv, sad, sdd;
 };
 
+// View groups of the staged adjoint gather (depth a multiple of 32): small grids have few
+// 16 x 16 x 32 tiles, so the views are split into groups (one work-group per tile and group,
+// about 2048 in all) whose partial volumes are summed in group order.
+inline int cbct_adj_vsplit(int nx, int ny, int nz, int nviews) {
+    if (nz % 32 != 0) return 1;
+    const long tiles = (long)((nx + 15) / 16) * ((ny + 15) / 16) * (nz / 32);
+    long vs = 2048 / std::max(tiles, 1L);
+    vs = std::min(vs, std::min<long>(16, nviews));
+    return (int)std::max(vs, 1L);
+}
+
 // Where the z profiles of one (view, column) live in the adjoint's workspace: samples
 // k0 .. k0+nk-1 (those whose transverse position is within one voxel of the grid), nz floats each.
 struct ZIndex {
-    long off;  // float offset, a multiple of 4
+    long off;  // float offset, a multiple of 32
     int k0, nk;
 };
 static_assert(sizeof(ZIndex) == 16, "ZIndex layout");
@@ -55,7 +67,9 @@ struct Level {
     int fwd_tw;    // table rows (z cells incl. padding)
     // adjoint
     AdjArgs adj;
-    long z_floats = 0;            // size of the profile workspace
+    long z_floats = 0;            // size of the adjoint workspace (profiles + view-group partials)
+    int adj_vsplit = 1;           // view groups of the staged gather
+    long adj_part_off = 0;        // float offset of the view-group partial volumes
     ZIndex *d_zix = nullptr;      // [nviews][nu]
     double schur_t = 0.0;  // cached Schur-bound step (0: not computed yet)
     // device tables
@@ -92,8 +106,16 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
                                 float *out, float *Zws, hipStream_t s, bool preweighted = false);
 
 // ---- solver pieces --------------------------------------------------------------------------
-constexpr int CBCT_RED_BLOCKS = 1024;  // work-groups of the fixed-size reduction grids
+constexpr int CBCT_RED_BLOCKS = 8192;  // work-groups of the fixed-size reduction grids
 constexpr int CBCT_TRIALS = 4;         // Armijo step sizes evaluated per trial pass
+
+// The hardware deals the work-groups of a launch round-robin to the 8 XCDs, each with its own L2.
+// Remapping the linear work-group index w -> (w mod 8) (G / 8) + w / 8 hands every XCD a
+// contiguous range instead, so work-groups that read neighbouring data share one L2 (identity
+// unless G is a multiple of 8).
+__device__ __forceinline__ int cbct_xcd_remap(int w, int G) {
+    return (G & 7) ? w : (w & 7) * (G >> 3) + (w >> 3);
+}
 
 // Device-side result of one Armijo search window (read by the host after each ROF iteration).
 struct RofControl {

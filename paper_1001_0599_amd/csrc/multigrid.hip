@@ -135,11 +135,18 @@ __global__ void __launch_bounds__(256) k_max_part(const float *__restrict__ x, l
     if (threadIdx.x == 0) part[blockIdx.x] = (double)sh[0];
 }
 
-__global__ void k_max_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// max is exact and order-free, so the split over threads keeps the result deterministic
+__global__ void __launch_bounds__(256) k_max_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    __shared__ double sh[256];
     double m = -1e300;
-    for (int b = 0; b < nb; b++) m = fmax(m, part[b]);
-    *out = m;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmax(m, part[b]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 int grid_for(long n) { return (int)std::min<long>(std::max<long>((n + 255) / 256, 1), 8192); }
@@ -190,7 +197,7 @@ cbct_status cbct_launch_max(const float *x, long n, double *partials, double *ou
     const int nb = (int)std::min<long>(std::max<long>((n + 255) / 256, 1), CBCT_RED_BLOCKS);
     hipLaunchKernelGGL(k_max_part, dim3(nb), dim3(256), 0, s, x, n, partials);
     LAUNCH_CHECK("k_max_part");
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(64), 0, s, partials, nb, out);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partials, nb, out);
     LAUNCH_CHECK("k_max_final");
     return CBCT_OK;
 }

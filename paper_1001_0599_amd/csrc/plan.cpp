@@ -145,7 +145,12 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     for (size_t q = 0; q < cols.size(); q++) {
         const int nk = std::max(cols[q].khi - cols[q].klo + 1, 0);
         zix[q] = ZIndex{zoff, cols[q].klo, nk};
-        zoff += ((long)nk * L.nz + 3) & ~3L;
+        zoff += ((long)nk * L.nz + 31) & ~31L;  // column blocks start on 128-byte lines
+    }
+    L.adj_vsplit = cbct_adj_vsplit(L.nx, L.ny, L.nz, L.nviews);
+    if (L.adj_vsplit > 1) {
+        L.adj_part_off = (zoff + 63) & ~63L;
+        zoff = L.adj_part_off + (long)L.adj_vsplit * L.nvox();
     }
     L.z_floats = std::max(zoff, 4L);
     AdjArgs &A = L.adj;

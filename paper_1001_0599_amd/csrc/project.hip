@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(256)
     int4 *ko = reinterpret_cast<int4 *>(kw + kc);
     __shared__ double wsum[4];
 
-    const int i = blockIdx.x, view = blockIdx.y;
+    // adjacent columns of one view sweep nearly the same voxels: keep them on one XCD
+    const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int i = w % nu, view = w / nu;
     const ColParams cp = cols[(long)view * nu + i];
     const int npairs = (nv + 1) >> 1;
     const int off = pad + 1;
@@ -83,6 +85,9 @@ __global__ void __launch_bounds__(256)
     }
 
     const int nzq = VEC ? (nz >> 2) : nz;
+    // this thread's first table item and the per-step advance (block size = dkk * nzq + dcq)
+    const int it0_kk = (int)threadIdx.x / nzq, it0_cq = (int)threadIdx.x - it0_kk * nzq;
+    const int dkk = (int)blockDim.x / nzq, dcq = (int)blockDim.x - dkk * nzq;
     for (int k0 = cp.klo; k0 <= cp.khi; k0 += KC) {
         constexpr int nk = KC;
         __syncthreads();  // previous chunk's rays are done with the tables
@@ -103,16 +108,25 @@ __global__ void __launch_bounds__(256)
                                         (bc1 * nx + ac1) * nz);
         }
         __syncthreads();
-        for (int it = threadIdx.x; it < nk * nzq; it += blockDim.x) {
-            const int kk = it / nzq, cq = it - kk * nzq;
+        // items (sample kk, cell group cq), cq fastest; the item index advances by the block size,
+        // so (kk, cq) advance by (dkk, dcq) with one carry (no division per item)
+        int ik = it0_kk, iq = it0_cq;
+        for (; ik < nk; ik += dkk, iq += dcq) {
+            if (iq >= nzq) {
+                iq -= nzq;
+                ik++;
+                if (ik >= nk) break;
+            }
+            const int kk = ik, cq = iq;
             const float4 w = kw[kk];
             const int4 o = ko[kk];
             if (VEC) {
                 const int c = cq << 2;
-                const float4 v0 = *reinterpret_cast<const float4 *>(vol_t + o.x + c);
-                const float4 v1 = *reinterpret_cast<const float4 *>(vol_t + o.y + c);
-                const float4 v2 = *reinterpret_cast<const float4 *>(vol_t + o.z + c);
-                const float4 v3 = *reinterpret_cast<const float4 *>(vol_t + o.w + c);
+                const float *vc = vol_t + c;  // column offsets are non-negative: zero-extended adds
+                const float4 v0 = *reinterpret_cast<const float4 *>(vc + (unsigned)o.x);
+                const float4 v1 = *reinterpret_cast<const float4 *>(vc + (unsigned)o.y);
+                const float4 v2 = *reinterpret_cast<const float4 *>(vc + (unsigned)o.z);
+                const float4 v3 = *reinterpret_cast<const float4 *>(vc + (unsigned)o.w);
                 float col[4];
                 col[0] = fmaf(w.w, v3.x, fmaf(w.z, v2.x, fmaf(w.y, v1.x, w.x * v0.x)));
                 col[1] = fmaf(w.w, v3.y, fmaf(w.z, v2.y, fmaf(w.y, v1.y, w.x * v0.y)));
@@ -147,12 +161,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int p = 0; p < NPT; p++) {
                 const float s = fmaf((float)kk, ds[p], sb[p]);  // > 0: the tables are padded
-                const float fz = __builtin_amdgcn_fractf(s);
+                const float fz = __builtin_amdgcn_fractf(s), gz = 1.0f - fz;
                 const int e = (int)s;
                 const float *t = tab + __mul24(e, S) + kk;
                 const float t0 = t[0], t1 = t[S], r0 = t[kc], r1 = t[kc + S];
-                acc_t[p] += fmaf(fz, t1 - t0, t0);
-                acc_r[p] += fmaf(fz, r1 - r0, r0);
+                acc_t[p] = fmaf(fz, t1, fmaf(gz, t0, acc_t[p]));
+                acc_r[p] = fmaf(fz, r1, fmaf(gz, r0, acc_r[p]));
             }
         }
     }

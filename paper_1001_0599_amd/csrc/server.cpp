@@ -76,10 +76,19 @@ size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<in
     size_t parts = (size_t)CBCT_RED_BLOCKS * (3 + 2 * CBCT_TRIALS);
     parts = std::max(parts, (size_t)g.n_views * g.nu);
     b += align256(8 * parts) + align256(8 * 64);
-    // adjoint profiles: at most (grid support diagonal / sample step + 3) samples per column
-    const double dtau = (g.sample_ratio > 0 ? g.sample_ratio : 1.0) * std::min(g.hx, g.hy);
-    const double diag = std::sqrt(std::pow((g.nx + 2) * g.hx, 2) + std::pow((g.ny + 2) * g.hy, 2));
-    b += align256(4 * (size_t)g.n_views * g.nu * ((size_t)std::ceil(diag / dtau) + 4) * (size_t)(g.nz + 3));
+    // adjoint workspace, the largest over the levels: profiles (at most grid support diagonal /
+    // sample step + 3 samples per column) and the view-group partial volumes
+    size_t zmax = 0;
+    for (int l = 0; l < levels; l++) {
+        const int nx = g.nx >> l, ny = g.ny >> l, nz = g.nz >> l, nu = g.nu >> l;
+        const double hx = g.hx * (1 << l), hy = g.hy * (1 << l);
+        const double dtau = (g.sample_ratio > 0 ? g.sample_ratio : 1.0) * std::min(hx, hy);
+        const double diag = std::sqrt(std::pow((nx + 2) * hx, 2) + std::pow((ny + 2) * hy, 2));
+        const size_t zf = (size_t)g.n_views * nu * (((size_t)std::ceil(diag / dtau) + 4) * (size_t)nz + 32) + 64 +
+                          (size_t)cbct_adj_vsplit(nx, ny, nz, g.n_views) * nx * ny * nz;
+        zmax = std::max(zmax, zf);
+    }
+    b += align256(4 * zmax);
     int slots = 0;
     for (int l = 0; l < levels; l++) slots += iters[l] + 1;
     b += align256(16 * (size_t)std::max(slots, 1)) + align256(sizeof(RofControl));

@@ -356,6 +356,12 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
     return CBCT_OK;
 }
 
+extern "C" cbct_status cbct_tv_energy_grad_workspace_size(const cbct_plan *p, size_t *bytes) {
+    if (!p || !bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad_workspace_size: NULL argument");
+    *bytes = sizeof(double) * (CBCT_RED_BLOCKS * 3 + 8);
+    return CBCT_OK;
+}
+
 extern "C" cbct_status cbct_tv_energy_grad(cbct_plan *p, int level, double tv_eps, const float *d_f, float *d_grad,
                                            double *h_sum, void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
     if (!p || !d_f || !d_ws || level < 0 || level >= p->levels || !(tv_eps > 0.0))

@@ -219,7 +219,9 @@ class Plan:
         _require(f, self.vol_shape(level), "f", self.device)
         if grad is None:
             grad = torch.empty_like(f)
-        nb = 8 * (3 * 1024 + 8)
+        n = C.c_size_t()
+        check(lib().cbct_tv_energy_grad_workspace_size(self._h, C.byref(n)))
+        nb = int(n.value)
         if workspace is None or workspace.numel() * workspace.element_size() < nb:
             workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
         h = C.c_double()
