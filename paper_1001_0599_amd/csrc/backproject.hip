@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(256)
 // loads (8 lanes per row), and every voxel column then gathers its hits from LDS.  Each profile
 // line is read from L2 once per tile and view instead of once per voxel that uses it.
 #ifndef CBCT_GS_ROWS
-#define CBCT_GS_ROWS 224
+#define CBCT_GS_ROWS 288
 #endif
 constexpr int GS_TZ = 32;              // z cells per tile
 constexpr int GS_ROWS = CBCT_GS_ROWS;  // staged rows per batch
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256)
                         const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
                         int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
                         float *__restrict__ part) {
-    __shared__ float4 zs[GS_ROWS * GS_PITCH];
+    __shared__ float4 zs[(GS_ROWS + 1) * GS_PITCH];  // + one spill row for the staging's idle slots
     __shared__ GsCol ci[GS_CC];
     __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
     __shared__ long rowsrc[GS_ROWS];  // profile offset of each staged row
@@ -367,10 +367,31 @@ __global__ void __launch_bounds__(256)
                     for (int r = r_a; r < r_b; r++) rowsrc[r - R0] = z0 + (long)r * A.nz;
                 }
                 __syncthreads();
-                // stage the rows: 8 lanes per 128-byte row
-                for (int it = tid; it < nrows * (GS_TZ / 4); it += blockDim.x) {
-                    const int r = it >> 3, q = it & 7;
-                    zs[r * GS_PITCH + q] = *reinterpret_cast<const float4 *>(Z + rowsrc[r] + 4 * q);
+                // stage the rows: 8 lanes per 128-byte row; every load of the batch is issued
+                // before the first LDS store, so the batch pays one memory latency
+                {
+                    constexpr int PER = (GS_ROWS * (GS_TZ / 4) + 255) / 256;
+                    const int items = nrows * (GS_TZ / 4);  // > 0
+                    float4 v[PER];
+#pragma unroll
+                    for (int j = 0; j < PER; j++) {
+                        // items past the batch load its last row again (no branch between the loads)
+                        const int it = min(tid + 256 * j, items - 1);
+                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> 3] + 4 * (it & 7));
+                    }
+                    // all loads in flight before the first store: an empty asm statement consumes
+                    // every loaded word here, so the compiler cannot sink (or split) each load
+                    // down to its store; idle slots store into the spill row
+                    float dep = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < PER; j++) dep += (v[j].x + v[j].y) + (v[j].z + v[j].w);
+                    asm volatile("" ::"v"(dep));
+#pragma unroll
+                    for (int j = 0; j < PER; j++) {
+                        const int it = tid + 256 * j;
+                        const int r = it < items ? (it >> 3) : GS_ROWS;
+                        zs[r * GS_PITCH + (it & 7)] = v[j];
+                    }
                 }
                 __syncthreads();
                 if (inside) {
