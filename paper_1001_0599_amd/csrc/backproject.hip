@@ -31,8 +31,9 @@ namespace {
 template <bool PREWEIGHTED>
 __global__ void __launch_bounds__(256)
     k_adj_profiles(const float *__restrict__ proj, const ColParams *__restrict__ cols,
-                   const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, float *__restrict__ Z) {
-    extern __shared__ double2 ab[];  // [nv + 1]: (A, B)
+                   const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, bool gb_lds,
+                   float *__restrict__ Z) {
+    extern __shared__ double2 ab[];  // [nv + 1]: (A, B), then [max nk] per-sample constants
     __shared__ double wtot[4][2];
     // adjacent columns share the cache lines of their projection rows: keep them on one XCD
     const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
@@ -94,11 +95,35 @@ __global__ void __launch_bounds__(256)
     const int nq = (nz + CG - 1) / CG;
     const bool vec = (nz & 3) == 0;
     float *zc = Z + zi.off;
-    for (int it = tid; it < zi.nk * nq; it += blockDim.x) {
-        const int kk = it / nq, cg0 = (it - kk * nq) * CG;
+    // per sample: 1 / gamma and iv - beta / gamma, once (an FP64 division is a long sequence),
+    // when the column's samples fit in LDS
+    double2 *gb = ab + (nv + 1);
+    if (gb_lds) {
+        for (int kk = tid; kk < zi.nk; kk += blockDim.x) {
+            const double ig = 1.0 / (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
+            gb[kk] = make_double2(ig, (double)iv - beta * ig);
+        }
+        __syncthreads();
+    }
+    // items it = tid + m * blockDim: (kk, cq) advance by (dkk, dcq) with one carry
+    const int dkk = (int)blockDim.x / nq, dcq = (int)blockDim.x - dkk * nq;
+    int kk = tid / nq, cq = tid - kk * nq;
+    for (; kk < zi.nk; kk += dkk, cq += dcq) {
+        if (cq >= nq) {
+            cq -= nq;
+            if (++kk >= zi.nk) break;
+        }
+        const int cg0 = cq * CG;
         const double gamma = (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
-        const double ig = 1.0 / gamma;
-        const double base = (double)iv - beta * ig;
+        double ig, base;
+        if (gb_lds) {
+            const double2 gbk = gb[kk];
+            ig = gbk.x;
+            base = gbk.y;
+        } else {
+            ig = 1.0 / gamma;
+            base = (double)iv - beta * ig;
+        }
         double2 pr[CG + 2];
 #pragma unroll
         for (int q = 0; q < CG + 2; q++) {
@@ -477,14 +502,16 @@ cbct_status launch_gather(const Level &L, const float *Z, const float *fbase, fl
 
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
                                 float *Zws, hipStream_t s, bool preweighted) {
-    const size_t lds = sizeof(double2) * (L.nv + 1);
+    size_t lds = sizeof(double2) * (L.nv + 1 + L.zk_max);
+    const bool gb_lds = lds <= 64 * 1024;
+    if (!gb_lds) lds = sizeof(double2) * (L.nv + 1);
     dim3 g1(L.nu, L.nviews);
     if (preweighted)
         hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
-                           (float)L.pv, Zws);
+                           (float)L.pv, gb_lds, Zws);
     else
         hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
-                           (float)L.pv, Zws);
+                           (float)L.pv, gb_lds, Zws);
     LAUNCH_CHECK("k_adj_profiles");
     const int nz = L.nz;
     if (nz % GS_TZ == 0) {

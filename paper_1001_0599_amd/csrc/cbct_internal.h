@@ -68,6 +68,7 @@ struct Level {
     // adjoint
     AdjArgs adj;
     long z_floats = 0;            // size of the adjoint workspace (profiles + view-group partials)
+    int zk_max = 0;               // most samples of one column inside the grid's support
     int adj_vsplit = 1;           // view groups of the staged gather
     long adj_part_off = 0;        // float offset of the view-group partial volumes
     ZIndex *d_zix = nullptr;      // [nviews][nu]

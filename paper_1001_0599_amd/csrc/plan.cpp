@@ -145,6 +145,7 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     for (size_t q = 0; q < cols.size(); q++) {
         const int nk = std::max(cols[q].khi - cols[q].klo + 1, 0);
         zix[q] = ZIndex{zoff, cols[q].klo, nk};
+        L.zk_max = std::max(L.zk_max, nk);
         zoff += ((long)nk * L.nz + 31) & ~31L;  // column blocks start on 128-byte lines
     }
     L.adj_vsplit = cbct_adj_vsplit(L.nx, L.ny, L.nz, L.nviews);

@@ -67,7 +67,8 @@ __device__ __forceinline__ void diffs_step(const float *__restrict__ u, const fl
 }
 
 __device__ __forceinline__ float phi_of(float dx, float dy, float dz, float eps2) {
-    return sqrtf(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2))));
+    // hardware square root (1 ulp): the argument is at least eps^2, a normal number
+    return __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2))));
 }
 
 // Work distribution of the TV kernels: lanes run along x (64 per row segment), work-groups take
@@ -104,23 +105,23 @@ __global__ void __launch_bounds__(256) k_tv_grad(const float *__restrict__ u, co
             float dx, dy, dz;
             diffs(u, p, a, b, c, k, dx, dy, dz);
             const float ph = phi_of(dx, dy, dz, k.eps2);
-            const float ip = 1.0f / ph;
+            const float ip = __builtin_amdgcn_rcpf(ph);  // 1 ulp reciprocals instead of divisions
             // the z difference of the last plane is identically 0 (reflective ghost): q_z = 0 there
             float div = -(dx * ip * k.ihx + dy * ip * k.ihy + dz * ip * k.ihz);
             if (a >= 1) {
                 float ex, ey, ez;
                 diffs(u, p - 1, a - 1, b, c, k, ex, ey, ez);
-                div += ex / phi_of(ex, ey, ez, k.eps2) * k.ihx;
+                div += ex * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihx;
             }
             if (b >= 1) {
                 float ex, ey, ez;
                 diffs(u, p - k.nx, a, b - 1, c, k, ex, ey, ez);
-                div += ey / phi_of(ex, ey, ez, k.eps2) * k.ihy;
+                div += ey * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihy;
             }
             if (c >= 1) {
                 float ex, ey, ez;
                 diffs(u, p - nxy, a, b, c - 1, k, ex, ey, ez);
-                div += ez / phi_of(ex, ey, ez, k.eps2) * k.ihz;
+                div += ez * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihz;
             }
             float dv;
             if (g) {
@@ -211,25 +212,33 @@ __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, c
     }
 }
 
-// in-order sum of `nb` rows of `width` partials: out[j] = sum_b part[b * width + j]
+// sum of `nb` rows of `width` partials: out[j] = sum_b part[b * width + j], in a fixed order
+// (each thread sums a contiguous run of rows, then a fixed binary tree over the threads), so the
+// result does not depend on timing
+constexpr int SUM_MAXW = 3 + 2 * CBCT_TRIALS;
 __global__ void __launch_bounds__(256) k_sum_rows(const double *__restrict__ part, int nb, int width,
                                                   double *__restrict__ out) {
-    __shared__ double sh[256];
-    for (int j = 0; j < width; j++) {
-        // each thread sums a contiguous run of rows; runs are then added in thread order
-        const int per = (nb + blockDim.x - 1) / blockDim.x;
-        const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
-        double s = 0.0;
-        for (int b = b0; b < b1; b++) s += part[(long)b * width + j];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int q = 0; q < (int)blockDim.x; q++) t += sh[q];
-            out[j] = t;
-        }
+    __shared__ double sh[SUM_MAXW][256];
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    double s[SUM_MAXW];
+#pragma unroll
+    for (int j = 0; j < SUM_MAXW; j++) s[j] = 0.0;
+    for (int b = b0; b < b1; b++) {
+#pragma unroll
+        for (int j = 0; j < SUM_MAXW; j++)
+            if (j < width) s[j] += part[(long)b * width + j];
+    }
+#pragma unroll
+    for (int j = 0; j < SUM_MAXW; j++)
+        if (j < width) sh[j][threadIdx.x] = s[j];
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int j = 0; j < width; j++) sh[j][threadIdx.x] += sh[j][threadIdx.x + o];
         __syncthreads();
     }
+    if ((int)threadIdx.x < width) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void k_axpy_step(float *__restrict__ u, const float *__restrict__ d, const RofControl *__restrict__ ctl,
@@ -352,6 +361,7 @@ cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ct
 }
 
 cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s) {
+    if (width < 1 || width > SUM_MAXW) return cbct_set_error(CBCT_ERR_INVALID_ARG, "sum_rows: width %d", width);
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, part, nb, width, out);
     LAUNCH_CHECK("k_sum_rows");
     return CBCT_OK;
