@@ -287,13 +287,11 @@ __global__ void __launch_bounds__(256)
 // samples of each inside the box (+ one voxel), stages those profile rows in LDS with coalesced
 // loads (8 lanes per row), and every voxel column then gathers its hits from LDS.  Each profile
 // line is read from L2 once per tile and view instead of once per voxel that uses it.
-#ifndef CBCT_GS_ROWS
-#define CBCT_GS_ROWS 288
-#endif
-constexpr int GS_TZ = 32;              // z cells per tile
-constexpr int GS_ROWS = CBCT_GS_ROWS;  // staged rows per batch
-constexpr int GS_CC = 64;              // detector columns per column chunk (one wave lists them)
-constexpr int GS_PITCH = GS_TZ / 4 + 1;  // float4 slots per staged row (one pad slot against bank conflicts)
+// Tiles of 32 z cells stage 288 rows per batch (3 work-groups per CU).  Measured on MI355X:
+// 224 rows 2.42 ms, 288 rows 2.17 ms, 448 rows 3.46 ms per P^T at 512x512x64 / 40 views; tiles of
+// 64 cells (whole profile rows, 2 work-groups per CU) were slower than 32 (2.16 vs 1.99 ms).
+constexpr int GS_ROWS32 = 288;
+constexpr int GS_CC = 64;  // detector columns per column chunk (one wave lists them)
 
 struct GsCol {
     float fx0, dfx, fy0, dfy, idfx, idfy;
@@ -303,11 +301,15 @@ struct GsCol {
 
 // With view groups (vgroups > 1) the work-group of group g covers views [g vper, (g+1) vper) and
 // writes its sums to part[g]; k_adj_combine adds the groups in order.
+template <int GS_TZ, int GS_ROWS>
 __global__ void __launch_bounds__(256)
     k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
                         const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
                         int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
                         float *__restrict__ part) {
+    constexpr int GS_Q = GS_TZ / 4;                 // float4 slots per profile row
+    constexpr int GS_QS = GS_TZ == 64 ? 4 : 3;      // log2(GS_Q)
+    constexpr int GS_PITCH = GS_Q + 1;              // one pad slot per staged row against bank conflicts
     __shared__ float4 zs[(GS_ROWS + 1) * GS_PITCH];  // + one spill row for the staging's idle slots
     __shared__ GsCol ci[GS_CC];
     __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
@@ -395,14 +397,14 @@ __global__ void __launch_bounds__(256)
                 // stage the rows: 8 lanes per 128-byte row; every load of the batch is issued
                 // before the first LDS store, so the batch pays one memory latency
                 {
-                    constexpr int PER = (GS_ROWS * (GS_TZ / 4) + 255) / 256;
-                    const int items = nrows * (GS_TZ / 4);  // > 0
+                    constexpr int PER = (GS_ROWS * GS_Q + 255) / 256;
+                    const int items = nrows * GS_Q;  // > 0
                     float4 v[PER];
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
                         // items past the batch load its last row again (no branch between the loads)
                         const int it = min(tid + 256 * j, items - 1);
-                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> 3] + 4 * (it & 7));
+                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1)));
                     }
                     // all loads in flight before the first store: an empty asm statement consumes
                     // every loaded word here, so the compiler cannot sink (or split) each load
@@ -414,8 +416,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
                         const int it = tid + 256 * j;
-                        const int r = it < items ? (it >> 3) : GS_ROWS;
-                        zs[r * GS_PITCH + (it & 7)] = v[j];
+                        const int r = it < items ? (it >> GS_QS) : GS_ROWS;
+                        zs[r * GS_PITCH + (it & (GS_Q - 1))] = v[j];
                     }
                 }
                 __syncthreads();
@@ -440,7 +442,7 @@ __global__ void __launch_bounds__(256)
                                 fmaxf(1.0f - fabsf(fx - (float)a), 0.0f) * fmaxf(1.0f - fabsf(fy - (float)b), 0.0f);
                             const float4 *zr = zs + (rbase + k) * GS_PITCH;
 #pragma unroll
-                            for (int q = 0; q < GS_TZ / 4; q++) {
+                            for (int q = 0; q < GS_Q; q++) {
                                 const float4 z4 = zr[q];
                                 acc[4 * q + 0] = fmaf(wxy, z4.x, acc[4 * q + 0]);
                                 acc[4 * q + 1] = fmaf(wxy, z4.y, acc[4 * q + 1]);
@@ -514,12 +516,13 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
                            (float)L.pv, gb_lds, Zws);
     LAUNCH_CHECK("k_adj_profiles");
     const int nz = L.nz;
-    if (nz % GS_TZ == 0) {
+    const int tzs = cbct_adj_staged_tz(nz);  // 32 or 0
+    if (tzs) {
         const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
         float *part = Zws + L.adj_part_off;
-        dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / GS_TZ) * vg);
-        hipLaunchKernelGGL(k_adj_gather_staged, grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix, L.d_cols, L.d_views,
-                           L.adj, vg, vper, fbase, kappa, out, part);
+        dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / tzs) * vg);
+        hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix,
+                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part);
         LAUNCH_CHECK("k_adj_gather_staged");
         if (vg > 1) {
             const long n = L.nvox();

@@ -41,9 +41,13 @@ struct AdjArgs {
 // View groups of the staged adjoint gather (depth a multiple of 32): small grids have few
 // 16 x 16 x 32 tiles, so the views are split into groups (one work-group per tile and group,
 // about 2048 in all) whose partial volumes are summed in group order.
+// z cells per tile of the staged gather (0: depth not a multiple of 32, per-lane gather)
+inline int cbct_adj_staged_tz(int nz) { return nz % 32 == 0 ? 32 : 0; }
+
 inline int cbct_adj_vsplit(int nx, int ny, int nz, int nviews) {
-    if (nz % 32 != 0) return 1;
-    const long tiles = (long)((nx + 15) / 16) * ((ny + 15) / 16) * (nz / 32);
+    const int tz = cbct_adj_staged_tz(nz);
+    if (!tz) return 1;
+    const long tiles = (long)((nx + 15) / 16) * ((ny + 15) / 16) * (nz / tz);
     long vs = 2048 / std::max(tiles, 1L);
     vs = std::min(vs, std::min<long>(16, nviews));
     return (int)std::max(vs, 1L);

@@ -25,6 +25,11 @@ CASES = {
                                        pv=2.1, n_views=5, angles=(0.1, 1.0, 2.5, 3.9, 5.9)),
     "axis_aligned": dataclasses.replace(G1, n_views=4, angles=(0.0, np.pi / 2, np.pi, 1.5 * np.pi)),
     "tiny": dataclasses.replace(G1, nx=2, ny=3, nz=1, nu=3, nv=1, n_views=2),
+    # fine detector: a 16 x 16 voxel tile spans > 64 detector columns (several column chunks and
+    # several staged batches per view in the LDS gather)
+    "many_columns": dataclasses.replace(G1, nu=256, pu=0.3, nv=24, n_views=3, angles=(0.3, 2.0, 4.4)),
+    # 17 views over few tiles: the gather splits the views into groups, some of them empty
+    "view_groups": dataclasses.replace(G1, n_views=17),
     "cfg4_one": S.config_geometry("cfg4"),
 }
 
