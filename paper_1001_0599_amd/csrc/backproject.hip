@@ -287,9 +287,9 @@ __global__ void __launch_bounds__(256)
 // samples of each inside the box (+ one voxel), stages those profile rows in LDS with coalesced
 // loads (8 lanes per row), and every voxel column then gathers its hits from LDS.  Each profile
 // line is read from L2 once per tile and view instead of once per voxel that uses it.
-// Tiles of 32 z cells stage 288 rows per batch (3 work-groups per CU).  Measured on MI355X:
-// 224 rows 2.42 ms, 288 rows 2.17 ms, 448 rows 3.46 ms per P^T at 512x512x64 / 40 views; tiles of
-// 64 cells (whole profile rows, 2 work-groups per CU) were slower than 32 (2.16 vs 1.99 ms).
+// Tiles of 32 z cells stage 288 rows per batch (3 work-groups per CU): on MI355X at 512x512x64 /
+// 40 views this was the fastest of 160 to 448 rows, and faster than tiles of 64 cells (whole
+// profile rows, 2 work-groups per CU: 2.16 against 1.99 ms per P^T).
 constexpr int GS_ROWS32 = 288;
 constexpr int GS_CC = 64;  // detector columns per column chunk (one wave lists them)
 
