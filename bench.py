@@ -94,7 +94,7 @@ def serving_run(n_requests):
     import cbct_synth as S
     from paper_1001_0599_amd.serving import Server, replay, summarize
 
-    cfg = S.CONFIGS["cfg5"]
+    cfg = S.CONFIGS["serving_mix"]
     reqs = S.serving_requests(n_requests)
     log("serving: synthesising %d requests on the GPU" % n_requests)
     ys, outs = [], []
@@ -134,7 +134,7 @@ def kernels_only():
     from paper_1001_0599_amd.ops import Plan
 
     torch.cuda.set_device(0)
-    g = S.config_geometry("cfg2")
+    g = S.config_geometry("wide512x512x64")
     plan = Plan(g, levels=1)
     ph = S.make_phantom(g, 21)
     y = S.poisson_log_torch(S.analytic_projections_torch(g, ph, "cuda"), 1e5, 22).float().contiguous()
@@ -179,7 +179,7 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    cfg = S.CONFIGS["cfg2"]
+    cfg = S.CONFIGS["wide512x512x64"]
     g = cfg["geometry"]
     iters = cfg["iters"]
     lam = cfg["lam"]

@@ -93,21 +93,21 @@ def level_geometry(g: Geometry, level: int, bin_detector: bool = True) -> Geomet
 
 
 # --------------------------------------------------------------------------------------
-# Benchmark workloads (sizes from the paper's NCAT experiment scaled to the five
+# Workloads (sizes from the paper's NCAT experiment scaled to five
 # workload definitions; the phantoms below stand in for NCAT/CatPhan/patient data).
 # --------------------------------------------------------------------------------------
-_G1 = Geometry(32, 32, 32, 2.0, 2.0, 2.0, 64, 64, 1.5, 1.5, 1000.0, 1500.0, 16)
-_G2 = Geometry(512, 512, 64, 0.9, 0.9, 2.5, 512, 384, 0.78, 0.78, 1000.0, 1536.0, 40)
-_G4 = Geometry(128, 128, 128, 2.0, 2.0, 2.0, 256, 192, 2.0, 2.0, 1000.0, 1500.0, 60)
+_CUBE32 = Geometry(32, 32, 32, 2.0, 2.0, 2.0, 64, 64, 1.5, 1.5, 1000.0, 1500.0, 16)
+_WIDE512 = Geometry(512, 512, 64, 0.9, 0.9, 2.5, 512, 384, 0.78, 0.78, 1000.0, 1536.0, 40)
+_BATCH128 = Geometry(128, 128, 128, 2.0, 2.0, 2.0, 256, 192, 2.0, 2.0, 1000.0, 1500.0, 60)
 
 CONFIGS = {
-    "cfg1": dict(geometry=_G1, levels=1, iters=[20], lam=0.05, I0=1e5, seeds=(11, 12)),
-    "cfg2": dict(geometry=_G2, levels=2, iters=[20, 20], lam=0.05, I0=1e5, seeds=(21, 22)),
-    "cfg3": dict(geometry=_G1, levels=3, iters=[100, 100, 100], lam=(0.02, 0.05, 0.1), I0=2e3,
+    "cube32": dict(geometry=_CUBE32, levels=1, iters=[20], lam=0.05, I0=1e5, seeds=(11, 12)),
+    "wide512x512x64": dict(geometry=_WIDE512, levels=2, iters=[20, 20], lam=0.05, I0=1e5, seeds=(21, 22)),
+    "lowdose32": dict(geometry=_CUBE32, levels=3, iters=[100, 100, 100], lam=(0.02, 0.05, 0.1), I0=2e3,
                  seeds=(11, 32)),
-    "cfg4": dict(geometry=_G4, batch=8, lam=0.05, I0=1e5, phantom_seeds=tuple(range(41, 49)),
+    "batch8x128": dict(geometry=_BATCH128, batch=8, lam=0.05, I0=1e5, phantom_seeds=tuple(range(41, 49)),
                  noise_seed=49, perturb_seed=40, direction_seed=50),
-    "cfg5": dict(n_requests=256, rate=4.0, vol_types=((64, 64, 64), (128, 128, 128), (256, 256, 96)),
+    "serving_mix": dict(n_requests=256, rate=4.0, vol_types=((64, 64, 64), (128, 128, 128), (256, 256, 96)),
                  h=2.0, views=(20, 120), iters=[30], lam=0.05, I0=1e5, budget_bytes=200 * 10**9,
                  seeds=dict(arrivals=51, mix=52, phantom0=5000, noise0=6000)),
 }
@@ -330,7 +330,7 @@ def serving_requests(n: Optional[int] = None):
     over {64^3, 128^3, 256x256x96} at 2 mm and views uniform in [20, 120]
     (seed 52, drawn per request as type then views); detector Nu = 2 Nx,
     Nv = 2 Nz at 1.5 mm; SAD 1000 / SDD 1500."""
-    cfg = CONFIGS["cfg5"]
+    cfg = CONFIGS["serving_mix"]
     n = cfg["n_requests"] if n is None else n
     s = cfg["seeds"]
     ra = np.random.default_rng(s["arrivals"])

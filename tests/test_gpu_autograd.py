@@ -16,7 +16,7 @@ from tests.gpu_util import announce, rel_l2, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
-CFG = S.CONFIGS["cfg4"]
+CFG = S.CONFIGS["batch8x128"]
 G = CFG["geometry"]
 LAM = CFG["lam"]
 EPS = 1e-5

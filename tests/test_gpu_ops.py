@@ -16,9 +16,9 @@ from tests.gpu_util import announce, rel_l2, to_gpu, to_np
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
-G1 = S.config_geometry("cfg1")
+G1 = S.config_geometry("cube32")
 CASES = {
-    "cfg1": G1,
+    "cube32": G1,
     # ragged: sizes not multiples of the tiles, odd detector rows, nz not a multiple of 4
     "ragged": dataclasses.replace(G1, nx=23, ny=19, nz=13, nu=37, nv=29, n_views=7),
     "anisotropic": dataclasses.replace(G1, nx=40, ny=24, nz=18, hx=1.5, hy=2.5, hz=3.0, nu=50, nv=31, pu=1.3,
@@ -30,7 +30,7 @@ CASES = {
     "many_columns": dataclasses.replace(G1, nu=256, pu=0.3, nv=24, n_views=3, angles=(0.3, 2.0, 4.4)),
     # 17 views over few tiles: the gather splits the views into groups, some of them empty
     "view_groups": dataclasses.replace(G1, n_views=17),
-    "cfg4_one": S.config_geometry("cfg4"),
+    "batch128_one": S.config_geometry("batch8x128"),
 }
 
 
@@ -66,7 +66,7 @@ def test_adjoint_matches_oracle(name):
         assert e < TOL, (name, kind, e)
 
 
-@pytest.mark.parametrize("name", ["cfg1", "ragged", "cfg4_one"])
+@pytest.mark.parametrize("name", ["cube32", "ragged", "batch128_one"])
 def test_gpu_adjoint_identity(name):
     g = CASES[name]
     plan = _plan(g)
@@ -79,8 +79,8 @@ def test_gpu_adjoint_identity(name):
 
 def test_forward_full_size_sampled():
     """512x512x64, 40 views, 512x384 detector (both multigrid levels): sampled rays."""
-    g = S.config_geometry("cfg2")
-    announce("forward full-size cfg2 sampled")
+    g = S.config_geometry("wide512x512x64")
+    announce("forward full-size 512x512x64 sampled")
     plan = _plan(g, levels=2)
     rng = np.random.default_rng(0)
     ph = S.make_phantom(g, 21)
@@ -95,8 +95,8 @@ def test_forward_full_size_sampled():
 
 
 def test_adjoint_full_size_sampled():
-    g = S.config_geometry("cfg2")
-    announce("adjoint full-size cfg2 sampled")
+    g = S.config_geometry("wide512x512x64")
+    announce("adjoint full-size 512x512x64 sampled")
     plan = _plan(g, levels=2)
     rng = np.random.default_rng(1)
     for level in (0, 1):
@@ -114,7 +114,7 @@ def test_adjoint_full_size_sampled():
 def test_full_size_adjoint_identity():
     """<Px, y> = <x, P^T y> at 512x512x64 / 40 views: relative 2e-5 for non-negative inputs,
     and |<Px,y> - <x,P^T y>| <= 1e-6 |Px| |y| for signed inputs (their inner products cancel)."""
-    g = S.config_geometry("cfg2")
+    g = S.config_geometry("wide512x512x64")
     plan = _plan(g)
     for kind, tol in (("uniform", 2e-5), ("normal", 1e-6)):
         x = to_gpu(S.random_volume(g, 12, kind))

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _requests():
-    base = S.config_geometry("cfg1")
+    base = S.config_geometry("cube32")
     geos = [dataclasses.replace(base, n_views=nv, nx=n, ny=n, nz=nz, nu=2 * n, nv=2 * nz)
             for nv, n, nz in ((16, 32, 32), (24, 48, 32), (12, 32, 16), (20, 64, 32), (16, 32, 32), (30, 48, 16))]
     reqs = []

@@ -18,9 +18,9 @@ from tests.gpu_util import announce, rel_l2, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
-G1 = S.config_geometry("cfg1")
+G1 = S.config_geometry("cube32")
 # the 512x512x64 / 40-view workload at 1/4 resolution per axis in x, y and detector
-G2Q = dataclasses.replace(S.config_geometry("cfg2"), nx=128, ny=128, nz=16, hx=3.6, hy=3.6, hz=10.0, nu=128, nv=96,
+G2Q = dataclasses.replace(S.config_geometry("wide512x512x64"), nx=128, ny=128, nz=16, hx=3.6, hy=3.6, hz=10.0, nu=128, nv=96,
                           pu=3.12, pv=3.12)
 
 
@@ -29,7 +29,7 @@ def _plan(g, levels=1):
     return Plan(g, levels=levels)
 
 
-def _cfg1_y(I0=1e5, noise_seed=12):
+def _cube32_y(I0=1e5, noise_seed=12):
     ph = S.make_phantom(G1, 11)
     return S.poisson_log(S.analytic_projections(G1, ph), I0, noise_seed)
 
@@ -105,9 +105,9 @@ def _compare_solve(g, Y, lam, iters, levels, step=0.0):
     return e, replayed, res, st
 
 
-def test_reconstruct_cfg1_matches_oracle():
+def test_reconstruct_cube32_matches_oracle():
     announce("reconstruct 32^3, 16 views, 20 iterations")
-    Y = _cfg1_y()
+    Y = _cube32_y()
     e, replayed, res, st = _compare_solve(G1, Y, 0.05, [20], 1)
     assert e < 1e-3, (e, replayed)
     # t per level and the energy trace agree too
@@ -119,7 +119,7 @@ def test_reconstruct_cfg1_matches_oracle():
 @pytest.mark.parametrize("lam", [0.02, 0.05, 0.1])
 def test_reconstruct_low_dose_3_levels(lam):
     announce("reconstruct low dose, 3 levels x 100 iterations, lambda %g" % lam)
-    Y = _cfg1_y(I0=2e3, noise_seed=32)
+    Y = _cube32_y(I0=2e3, noise_seed=32)
     e, replayed, res, st = _compare_solve(G1, Y, lam, [100, 100, 100], 3)
     assert e < 1e-3, (e, replayed)
 
@@ -134,7 +134,7 @@ def test_reconstruct_quarter_size_two_levels():
 
 def test_resume_and_determinism():
     """10 + 10 iterations via the start volume equal 20 iterations, bitwise; reruns are bitwise equal."""
-    Y = to_gpu(_cfg1_y())
+    Y = to_gpu(_cube32_y())
     plan = _plan(G1)
     t = 8.622563273966616e-05
     a = plan.reconstruct(Y, lam=0.05, iters=[20], step=t)
@@ -149,7 +149,7 @@ def test_full_size_solve_properties():
     """The 512x512x64 / 40-view workload, 2 levels: finite, non-negative, energy decreasing
     at each level, deterministic."""
     announce("reconstruct 512x512x64, 40 views, 2 levels x 4 iterations")
-    g = S.config_geometry("cfg2")
+    g = S.config_geometry("wide512x512x64")
     ph = S.make_phantom(g, 21)
     Y = to_gpu(S.poisson_log(S.analytic_projections(g, ph), 1e5, 22))
     plan = _plan(g, 2)

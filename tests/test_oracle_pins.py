@@ -17,7 +17,7 @@ import oracle as O
 from tests import brute
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
-G1 = S.config_geometry("cfg1")
+G1 = S.config_geometry("cube32")
 # tiny anisotropic grid, off-centre-sized detector, 3 views at irregular angles
 TINY = dataclasses.replace(G1, nx=5, ny=4, nz=3, hx=2.0, hy=1.5, hz=2.5, nu=6, nv=4, pu=3.0, pv=4.0,
                            n_views=3, angles=(0.3, 2.1, 4.4))
@@ -224,7 +224,7 @@ def pin_binning():
 
 
 # ------------------------------------------------------------------ solver pins
-def _cfg1_data():
+def _cube32_data():
     ph = S.make_phantom(G1, 11)
     return S.poisson_log(S.analytic_projections(G1, ph), 1e5, 12)
 
@@ -252,7 +252,7 @@ def pin_rof_armijo():
 def pin_fbs_monotone():
     """E(f_k) = D + lambda R is non-increasing over 20 outer iterations on the 32^3
     workload (slack 1e-9 E)."""
-    Y = _cfg1_data()
+    Y = _cube32_data()
     res = O.reconstruct(G1, Y, 0.05, [20], 1)
     e = res.energy
     viol = float(np.max(np.diff(e) - 1e-9 * e[:-1]))
@@ -277,7 +277,7 @@ def pin_nnls():
 
 def pin_resume():
     """10 + 10 outer iterations through d_init equal 20 iterations (oracle: 1e-15)."""
-    Y = _cfg1_data()
+    Y = _cube32_data()
     t = O.schur_step(G1)
     a = O.reconstruct(G1, Y, 0.05, [20], 1, step=t).f
     b1 = O.reconstruct(G1, Y, 0.05, [10], 1, step=t).f

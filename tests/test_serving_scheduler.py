@@ -11,7 +11,7 @@ import cbct_synth as S
 from paper_1001_0599_amd import CbctError
 from paper_1001_0599_amd.serving import Server
 
-G = dataclasses.replace(S.config_geometry("cfg1"), n_views=8)  # ~17 MB of workspace
+G = dataclasses.replace(S.config_geometry("cube32"), n_views=8)  # ~17 MB of workspace
 
 
 def _bytes_one():

@@ -7,7 +7,7 @@ import cbct_synth as S
 
 
 def test_phantom_values_and_seed():
-    g = S.config_geometry("cfg1")
+    g = S.config_geometry("cube32")
     ph = S.make_phantom(g, 11)
     assert len(ph) == 13
     vol = S.voxelize(g, ph, 2)
@@ -18,7 +18,7 @@ def test_phantom_values_and_seed():
 
 
 def test_inner_ellipsoids_inside_and_disjoint():
-    g = S.config_geometry("cfg2")
+    g = S.config_geometry("wide512x512x64")
     ph = S.make_phantom(g, 21)
     body = np.array(ph[0].axes)
     for i, e in enumerate(ph[1:]):
@@ -34,7 +34,7 @@ def test_inner_ellipsoids_inside_and_disjoint():
 
 
 def test_ball_chord_closed_form():
-    g = dataclasses.replace(S.config_geometry("cfg1"), n_views=3)
+    g = dataclasses.replace(S.config_geometry("cube32"), n_views=3)
     ball = S.Ellipsoid((3.0, -2.0, 1.0), (10.0, 10.0, 10.0), 0.4, 1.0)
     p = S.analytic_projections(g, [ball])
     Sx, D = S.ray_endpoints(g)
@@ -70,7 +70,7 @@ def test_serving_mix():
 
 def test_torch_projections_match_numpy():
     import torch
-    g = dataclasses.replace(S.config_geometry("cfg1"), n_views=3)
+    g = dataclasses.replace(S.config_geometry("cube32"), n_views=3)
     ph = S.make_phantom(g, 11)
     a = S.analytic_projections(g, ph)
     b = S.analytic_projections_torch(g, ph, "cpu").numpy()
