@@ -144,7 +144,7 @@ cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, con
                                  double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s);
 cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
                                    double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
-                                   hipStream_t s);
+                                   RofControl *mirror, hipStream_t s);
 cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ctl, long n, hipStream_t s);
 cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s);
 

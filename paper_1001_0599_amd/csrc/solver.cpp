@@ -21,6 +21,32 @@
 
 namespace {
 
+// Host-mapped pinned slot for the per-iteration decision record: the decision kernel writes it
+// directly, so the host needs no copy command before reading it (a copy into pageable memory is
+// staged through a runtime buffer on every ROF iteration).  One slot per host thread (the server
+// runs solves on several threads), allocated on first use and never freed: a free from a
+// thread-exit destructor could run after the HIP runtime has shut down.
+struct MappedSlot {
+    RofControl *host = nullptr, *dev = nullptr;
+};
+
+MappedSlot mapped_ctl() {
+    thread_local MappedSlot slot;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        void *h = nullptr, *d = nullptr;
+        if (hipHostMalloc(&h, sizeof(RofControl), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+            hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+            slot.host = (RofControl *)h;
+            slot.dev = (RofControl *)d;
+        } else {
+            (void)hipGetLastError();  // fall back to copies; do not leave the error pending
+        }
+    }
+    return slot;
+}
+
 std::mutex g_schur_mu;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -176,11 +202,17 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
             if ((st = cbct_launch_tv_trial(L, pr->tv_eps, b.u, b.d, b.g, t, pr->backtrack, m0, M, b.part, b.sums + 3,
                                            s)))
                 return st;
+            const MappedSlot ms = mapped_ctl();
             if ((st = cbct_launch_rof_decide(b.sums, m0, M, forced >= 0 ? forced : -1, L.nvox(), pr->lambda, t,
-                                             pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, s)))
+                                             pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, ms.dev, s)))
                 return st;
-            CBCT_HIP(hipMemcpyAsync(&c, b.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
-            CBCT_HIP(hipStreamSynchronize(s));
+            if (ms.host) {
+                CBCT_HIP(hipStreamSynchronize(s));
+                std::memcpy(&c, ms.host, sizeof(c));  // the kernel's writes are visible after the sync
+            } else {
+                CBCT_HIP(hipMemcpyAsync(&c, b.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+                CBCT_HIP(hipStreamSynchronize(s));
+            }
             if (c.accepted == 0 && c.next_m0 > m0) {
                 m0 = c.next_m0;
                 continue;

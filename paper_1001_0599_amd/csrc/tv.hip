@@ -251,33 +251,40 @@ __global__ void k_axpy_step(float *__restrict__ u, const float *__restrict__ d, 
 
 // Armijo decision for one ROF iteration from the reduced sums.
 // sums: [0..2] = {sum phi(u), sum (u-g)^2, sum d^2}, [3 + 2m + {0,1}] = trial sums for m - m0.
+// The record goes to ctl (read by the update kernel) and, when given, to a host-mapped mirror that
+// the host reads after synchronising the stream (no copy command).
 __global__ void k_rof_decide(const double *__restrict__ sums, int M, int m0, int forced_m, double inv_n, double lambda,
-                             double t, double c_armijo, double alpha, int max_bt, RofControl *__restrict__ ctl) {
+                             double t, double c_armijo, double alpha, int max_bt, RofControl *__restrict__ ctl,
+                             RofControl *__restrict__ mirror) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double e0 = lambda * sums[0] * inv_n + sums[1] * inv_n / (2.0 * t);
-    const double G = sums[2] * inv_n;
-    ctl->e0 = e0;
-    ctl->G = G;
-    ctl->accepted = 0;
-    ctl->next_m0 = -1;
+    RofControl r{};
+    r.e0 = lambda * sums[0] * inv_n + sums[1] * inv_n / (2.0 * t);
+    r.G = sums[2] * inv_n;
+    r.accepted = 0;
+    r.next_m0 = -1;
     double s = t;
     for (int m = 0; m < m0; m++) s *= alpha;
-    for (int q = 0; q < M && m0 + q <= max_bt; q++) {
+    bool done = false;
+    for (int q = 0; q < M && m0 + q <= max_bt && !done; q++) {
         const int m = m0 + q;
         const double e = lambda * sums[3 + 2 * q] * inv_n + sums[3 + 2 * q + 1] * inv_n / (2.0 * t);
-        ctl->e_trial = e;
-        ctl->m = m;
-        ctl->s = s;
-        const bool ok = (forced_m >= 0) ? (m == forced_m) : (e <= e0 - c_armijo * s * G);
+        r.e_trial = e;
+        r.m = m;
+        r.s = s;
+        const bool ok = (forced_m >= 0) ? (m == forced_m) : (e <= r.e0 - c_armijo * s * r.G);
         if (ok) {
-            ctl->accepted = 1;
-            return;
+            r.accepted = 1;
+            done = true;
         }
         s *= alpha;
     }
-    // none of this window satisfied the test: search further or give up
-    if (m0 + M <= max_bt && (forced_m < 0 || forced_m >= m0 + M)) ctl->next_m0 = m0 + M;
-    else ctl->accepted = -1;
+    if (!done) {
+        // none of this window satisfied the test: search further or give up
+        if (m0 + M <= max_bt && (forced_m < 0 || forced_m >= m0 + M)) r.next_m0 = m0 + M;
+        else r.accepted = -1;
+    }
+    *ctl = r;
+    if (mirror) *mirror = r;
 }
 
 }  // namespace
@@ -346,9 +353,9 @@ cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, con
 
 cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
                                    double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
-                                   hipStream_t s) {
+                                   RofControl *mirror, hipStream_t s) {
     hipLaunchKernelGGL(k_rof_decide, dim3(1), dim3(64), 0, s, sums, M, m0, forced_m, 1.0 / (double)nvox, lambda, t,
-                       c_armijo, alpha, max_bt, ctl);
+                       c_armijo, alpha, max_bt, ctl, mirror);
     LAUNCH_CHECK("k_rof_decide");
     return CBCT_OK;
 }
