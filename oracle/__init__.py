@@ -46,7 +46,7 @@ class Geom(C.Structure):
 class Params(C.Structure):
     _fields_ = [("lam", C.c_double), ("step", C.c_double), ("tv_eps", C.c_double),
                 ("armijo_c", C.c_double), ("backtrack", C.c_double), ("rof_tol", C.c_double),
-                ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int)]
+                ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int), ("step1_eq6", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -71,6 +71,7 @@ def lib():
             L.orc_forward_rays.argtypes = [P(Geom), _D, C.c_long, _L, _D]
             L.orc_adjoint.argtypes = [P(Geom), _D, _D]
             L.orc_adjoint_voxels.argtypes = [P(Geom), _D, C.c_long, _L, _D]
+            L.orc_backproject_eq6.argtypes = [P(Geom), _D, _D]
             L.orc_tv_energy.argtypes = [P(Geom), _D, C.c_double]
             L.orc_tv_energy.restype = C.c_double
             L.orc_tv_grad.argtypes = [P(Geom), _D, C.c_double, _D]
@@ -158,6 +159,16 @@ def adjoint(g, y) -> np.ndarray:
     return f
 
 
+def backproject_eq6(g, T) -> np.ndarray:
+    """The voxel-driven Eq. 6 backprojector (bilinear T at (u*, v*), weight L^3/(L0 l^2)),
+    scaled by hx hy hz / (pu pv)."""
+    h = _GeomHolder(g)
+    T = _f64(T).reshape(h.proj_shape)
+    f = np.empty(h.vol_shape)
+    lib().orc_backproject_eq6(h.ref(), _ptr(T), _ptr(f))
+    return f
+
+
 def adjoint_voxels(g, y, voxels) -> np.ndarray:
     h = _GeomHolder(g)
     y = _f64(y).reshape(h.proj_shape)
@@ -215,14 +226,15 @@ def bin_detector(Y, factor: int) -> np.ndarray:
     return out
 
 
-DEFAULTS = dict(tv_eps=1e-5, armijo_c=0.01, backtrack=0.6, rof_tol=1e-3, rof_max_iter=50, rof_max_backtrack=30)
+DEFAULTS = dict(tv_eps=1e-5, armijo_c=0.01, backtrack=0.6, rof_tol=1e-3, rof_max_iter=50, rof_max_backtrack=30,
+                step1_eq6=False)
 
 
 def _params(lam, step, **kw):
     p = dict(DEFAULTS)
     p.update(kw)
     return Params(float(lam), float(step), p["tv_eps"], p["armijo_c"], p["backtrack"], p["rof_tol"],
-                  int(p["rof_max_iter"]), int(p["rof_max_backtrack"]))
+                  int(p["rof_max_iter"]), int(p["rof_max_backtrack"]), int(bool(p["step1_eq6"])))
 
 
 class Result:

@@ -60,6 +60,7 @@ typedef struct {
     double rof_tol;       /* relative-decrease stop of Step 2 */
     int rof_max_iter;
     int rof_max_backtrack;
+    int step1_eq6;        /* 1: Step 1 uses the Eq. 6 backprojector instead of the exact P^T */
 } og_params;
 
 typedef struct {
@@ -275,6 +276,51 @@ void orc_adjoint(const og_geom *g, const double *y, double *f) {
     }
     for (int t = 0; t < nt; t++) free(buf[t]);
     free(buf);
+}
+
+/* The voxel-driven backprojector of Section II.C.2 (Eq. 6, with the Jacobian of Eq. A7):
+ * for every voxel centre V and view, the line from the source S through V meets the imager at
+ * (u*, v*) (Eq. A6 rotated by theta); T is sampled there by bilinear interpolation between
+ * pixel centres (zero beyond the imager) and weighted by L^3 / (L0 l^2), l = |V - S|,
+ * L = |P - S|, L0 = SDD.  Scaled by hx hy hz / (pu pv), which makes it the continuum limit
+ * of P^T (so it can stand in for P^T in Step 1 with the same step). */
+static double og_bilinear_det(const og_geom *g, const double *T, int view, double u, double v) {
+    double iu = u / g->pu + 0.5 * (g->nu - 1), iv = v / g->pv + 0.5 * (g->nv - 1);
+    int i0 = (int)floor(iu), j0 = (int)floor(iv);
+    double s = 0.0;
+    for (int j = j0; j <= j0 + 1; j++) {
+        if (j < 0 || j >= g->nv) continue;
+        for (int i = i0; i <= i0 + 1; i++) {
+            if (i < 0 || i >= g->nu) continue;
+            s += T[((long)view * g->nv + j) * g->nu + i] * og_hat(iu - i) * og_hat(iv - j);
+        }
+    }
+    return s;
+}
+
+void orc_backproject_eq6(const og_geom *g, const double *T, double *f) {
+    const double scale = g->hx * g->hy * g->hz / (g->pu * g->pv);
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < og_nvox(g); idx++) {
+        int a = (int)(idx % g->nx), b = (int)((idx / g->nx) % g->ny), c = (int)(idx / ((long)g->nx * g->ny));
+        double V[3] = {(a - 0.5 * (g->nx - 1)) * g->hx, (b - 0.5 * (g->ny - 1)) * g->hy,
+                       (c - 0.5 * (g->nz - 1)) * g->hz};
+        double acc = 0.0;
+        for (int view = 0; view < g->nviews; view++) {
+            double th = og_angle(g, view);
+            double ew[3] = {cos(th), sin(th), 0.0}, eu[3] = {sin(th), -cos(th), 0.0};
+            double S[3] = {-g->sad * ew[0], -g->sad * ew[1], 0.0};
+            double d[3] = {V[0] - S[0], V[1] - S[1], V[2] - S[2]};
+            double depth = d[0] * ew[0] + d[1] * ew[1];       /* along the central ray */
+            double us = g->sdd * (d[0] * eu[0] + d[1] * eu[1]) / depth;
+            double vs = g->sdd * d[2] / depth;
+            double l = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double L = sqrt(g->sdd * g->sdd + us * us + vs * vs);
+            const double jac = (og_fault == 12) ? L * L : L * L * L;
+            acc += jac / (g->sdd * l * l) * og_bilinear_det(g, T, view, us, vs);
+        }
+        f[idx] = scale * acc;
+    }
 }
 
 /* P^T at selected voxels (flat indices (c*ny + b)*nx + a).  Only rays whose pixel lies in
@@ -521,7 +567,8 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
         /* Step 1: gradient step on the data term, g = f - t N dD/df */
         double Dk = og_data_term(g, f, Y, r);
         og_energy_push(st, Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps));
-        orc_adjoint(g, r, pt);
+        if (pr->step1_eq6) orc_backproject_eq6(g, r, pt);
+        else orc_adjoint(g, r, pt);
         for (long v = 0; v < nvox; v++) gg[v] = (og_fault == 9) ? f[v] + kappa * pt[v] : f[v] - kappa * pt[v];
         /* Step 2: ROF */
         tc.outer = k;
