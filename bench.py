@@ -237,6 +237,27 @@ def main():
     torch.cuda.synchronize()
     tp = float(np.mean([a.elapsed_time(b) for a, b, _ in ev])) * 1e-3
     ta = float(np.mean([b.elapsed_time(c) for _, b, c in ev])) * 1e-3
+    # the paper's Eq. 6 backprojector alone, and the reconstruction with it in Step 1
+    for _ in range(3):
+        plan.backproject_eq6(Y, out=vol)
+    ev6 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_ev)]
+    for e0, e1 in ev6:
+        e0.record()
+        plan.backproject_eq6(Y, out=vol)
+        e1.record()
+    torch.cuda.synchronize()
+    tb6 = float(np.mean([a.elapsed_time(b) for a, b in ev6])) * 1e-3
+    params6, keep6 = plan.solve_params(lam, iters, step1_eq6=True)
+    ws6 = torch.empty(plan.reconstruct_workspace_bytes(params6), dtype=torch.uint8, device=dev)
+    plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=ws6, step1_eq6=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n6 = max(1, min(args.steps, 3))
+    for _ in range(n6):
+        plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=ws6, step1_eq6=True)
+    torch.cuda.synchronize()
+    recon6_s = (time.perf_counter() - t0) / n6
+    del ws6
     vv = g.n_vox * g.n_views
     # algorithmic bytes per launch: the volume read (P) or written (P^T) once per view, plus the
     # detector samples in and out (4 B each)
@@ -267,6 +288,7 @@ def main():
         "first_recon_s_incl_schur_probe": first_s,
         "p_voxel_views_per_s": vv / tp, "pt_voxel_views_per_s": vv / ta,
         "p_ms": tp * 1e3, "pt_ms": ta * 1e3,
+        "eq6_backprojector_ms": tb6 * 1e3, "recon_s_step1_eq6": recon6_s,
         "roofline": roofline,
     }
     if args.serving:

@@ -97,6 +97,16 @@ cbct_status cbct_forward(const cbct_plan *plan, int level, const float *d_vol, f
 cbct_status cbct_forward_columns(const cbct_plan *plan, int level, const float *d_vol_cols, float *d_proj,
                                  cbct_stream_t stream);
 
+/* The paper's voxel-driven backprojector (Section II.C.2, Eq. 6 with the Jacobian of Eq. A7):
+ * d_vol = B_level d_proj, where for every voxel centre V and view the line from the source
+ * through V meets the imager at (u*, v*) (Eq. A6), d_proj is sampled there by bilinear
+ * interpolation between pixel centres (zero beyond the imager) and weighted by L^3 / (L0 l^2);
+ * the sum over views is scaled by hx hy hz / (pu pv) (the continuum limit of P^T, not its exact
+ * transpose).  d_proj [n_views][nv][nu], d_vol [nz][ny][nx] at `level`, device memory.  No
+ * workspace, no atomics.  Errors: CBCT_ERR_INVALID_ARG for a NULL pointer or a bad level. */
+cbct_status cbct_backproject_eq6(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
+                                 cbct_stream_t stream);
+
 /* Workspace (device bytes) of cbct_adjoint at `level`: the z profiles of every detector
  * column's samples (views x columns x samples in the grid's support x nz floats). */
 cbct_status cbct_adjoint_workspace_size(const cbct_plan *plan, int level, size_t *bytes);
@@ -136,6 +146,8 @@ typedef struct {
     const int *replay;      /* NULL, or forced backtracking exponents, one per ROF iteration in order
                              * (-1: the search finds no step); used up first, then free running */
     int replay_len;
+    int step1_eq6;          /* 0 (default): Step 1 uses the exact P^T; 1: the Eq. 6 backprojector
+                             * (cbct_backproject_eq6) applied to P f - Y, with the same step */
 } cbct_solve_params;
 
 /* Optional diagnostics; arrays are caller-owned and may be NULL (lengths may exceed capacities:

@@ -39,7 +39,7 @@ class SolveParams(C.Structure):
     _fields_ = [("lam", C.c_double), ("iters", C.POINTER(C.c_int)), ("levels", C.c_int), ("step", C.c_double),
                 ("tv_eps", C.c_double), ("armijo_c", C.c_double), ("backtrack", C.c_double),
                 ("rof_tol", C.c_double), ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int),
-                ("replay", C.POINTER(C.c_int)), ("replay_len", C.c_int)]
+                ("replay", C.POINTER(C.c_int)), ("replay_len", C.c_int), ("step1_eq6", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -58,6 +58,7 @@ _SIG = [
     ("cbct_forward_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
     ("cbct_forward", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
     ("cbct_forward_columns", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
+    ("cbct_backproject_eq6", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_adjoint_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
     ("cbct_adjoint", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
     ("cbct_solve_params_default", None, [C.POINTER(SolveParams)]),

@@ -103,9 +103,13 @@ cbct_status cbct_hip_error(hipError_t e, const char *what);
 // kernel launchers (each checks its launch)
 cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_t, hipStream_t s);
 // y_sub == NULL: out = P f.  Otherwise residual mode: out = w * (P f - y_sub) (the ray weight
-// applied, ready for the pre-weighted adjoint) and partials[view * nu + i] = sum (P f - y_sub)^2.
+// applied, ready for the pre-weighted adjoint; plain P f - y_sub when weight_residual is false)
+// and partials[view * nu + i] = sum (P f - y_sub)^2.
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *y_sub, float *out,
-                                double *partials, hipStream_t s);
+                                double *partials, hipStream_t s, bool weight_residual = true);
+// out = B proj (f_base == NULL) or f_base - kappa B proj, B the Eq. 6 backprojector.
+cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const float *f_base, float kappa,
+                                        float *out, hipStream_t s);
 // out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
                                 float *out, float *Zws, hipStream_t s, bool preweighted = false);

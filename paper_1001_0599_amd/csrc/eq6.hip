@@ -1,0 +1,95 @@
+// The paper's voxel-driven backprojector (Section II.C.2, Eq. 6 with the Jacobian of Eq. A7): for
+// every voxel centre V and view, the line from the source through V meets the imager at
+// (u*, v*) (Eq. A6 rotated to the view); the detector image T is sampled there by bilinear
+// interpolation between pixel centres (zero beyond the imager) and weighted by
+// L^3 / (L0 l^2) = SDD^2 l / w^3, where w is V's depth along the central ray, l = |V - S| and
+// L = |P - S| = (SDD / w) l.  The sum over views is scaled by hx hy hz / (pu pv), which makes
+// the operator the continuum limit of P^T, so it can replace P^T in Step 1 with the same step.
+//
+// One thread per voxel column segment of 16 z cells, x fastest (lanes of a wave sample
+// neighbouring detector columns, which the caches serve): per view the column's u* terms are
+// computed once and each cell adds its v* row pair; all views in registers, one write per voxel.
+#include <hip/hip_runtime.h>
+
+#include "cbct_internal.h"
+
+namespace {
+
+constexpr int EQ6_ZC = 16;  // z cells per thread: the view's u-side terms are shared by them
+
+__global__ void __launch_bounds__(256)
+    k_backproject_eq6(const float *__restrict__ T, const ViewParams *__restrict__ views, AdjArgs A,
+                      const float *__restrict__ fbase, float kappa, float *__restrict__ out) {
+    const long ncol = (long)A.nx * A.ny;
+    const long tidg = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nzc = (A.nz + EQ6_ZC - 1) / EQ6_ZC;
+    if (tidg >= ncol * nzc) return;
+    const long colx = tidg % ncol;  // x fastest within a z chunk: neighbouring lanes, neighbouring columns
+    const int zc = (int)(tidg / ncol);
+    const int a = (int)(colx % A.nx), b = (int)(colx / A.nx);
+    const int c0 = zc * EQ6_ZC;
+    const float x = ((float)a - 0.5f * (float)(A.nx - 1)) * A.hx;
+    const float y = ((float)b - 0.5f * (float)(A.ny - 1)) * A.hy;
+    const float zc0 = ((float)c0 - 0.5f * (float)(A.nz - 1)) * A.hz;
+    const float cu = 0.5f * (float)(A.nu - 1), cv = 0.5f * (float)(A.nv - 1);
+    const float ipu = 1.0f / A.pu, ipv = 1.0f / A.pv;
+    const float sdd2 = A.sdd * A.sdd;
+    const long plane = (long)A.nu * A.nv;
+    float acc[EQ6_ZC];
+#pragma unroll
+    for (int q = 0; q < EQ6_ZC; q++) acc[q] = 0.0f;
+    for (int view = 0; view < A.nviews; view++) {
+        const ViewParams vp = views[view];
+        const float w = fmaf(x, vp.cs, fmaf(y, vp.sn, A.sad));  // depth of V beyond the source
+        const float t = fmaf(x, vp.sn, -y * vp.cs);             // offset along e_u
+        const float iw = 1.0f / w;
+        const float fu = fmaf(A.sdd * t * iw, ipu, cu);          // detector column coordinate of u*
+        const float fu0 = floorf(fu);
+        const int i0 = (int)fu0;
+        if (i0 < -1 || i0 >= A.nu) continue;
+        const float du = fu - fu0;
+        const float wu0 = (i0 >= 0) ? 1.0f - du : 0.0f, wu1 = (i0 + 1 < A.nu) ? du : 0.0f;
+        const int ia = max(i0, 0), ib = min(i0 + 1, A.nu - 1);
+        const float w2t2 = fmaf(w, w, t * t);
+        const float wk = sdd2 * iw * iw * iw;                    // L^3/(L0 l^2) = SDD^2 l / w^3
+        const float vstep = A.sdd * iw * ipv;                    // v* in rows per mm of z
+        const float *img = T + view * plane;
+#pragma unroll
+        for (int q = 0; q < EQ6_ZC; q++) {
+            const float z = fmaf((float)q, A.hz, zc0);
+            const float fv = fmaf(z, vstep, cv);
+            const float fv0 = floorf(fv);
+            const int j0 = (int)fv0;
+            const float dv = fv - fv0;
+            const float wv0 = (j0 >= 0 && j0 < A.nv) ? 1.0f - dv : 0.0f;
+            const float wv1 = (j0 + 1 >= 0 && j0 + 1 < A.nv) ? dv : 0.0f;
+            const float *r0 = img + (long)min(max(j0, 0), A.nv - 1) * A.nu;
+            const float *r1 = img + (long)min(max(j0 + 1, 0), A.nv - 1) * A.nu;
+            const float s = wv0 * fmaf(wu0, r0[ia], wu1 * r0[ib]) + wv1 * fmaf(wu0, r1[ia], wu1 * r1[ib]);
+            const float l = sqrtf(fmaf(z, z, w2t2));
+            acc[q] = fmaf(wk * l, s, acc[q]);
+        }
+    }
+    const float scale = A.hx * A.hy * A.hz * ipu * ipv;
+#pragma unroll
+    for (int q = 0; q < EQ6_ZC; q++) {
+        const int c = c0 + q;
+        if (c < A.nz) {
+            const long idx = ((long)c * A.ny + b) * A.nx + a;
+            const float v = acc[q] * scale;
+            out[idx] = fbase ? fmaf(-kappa, v, fbase[idx]) : v;
+        }
+    }
+}
+
+}  // namespace
+
+cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
+                                        hipStream_t s) {
+    const long n = (long)L.nx * L.ny * ((L.nz + EQ6_ZC - 1) / EQ6_ZC);
+    hipLaunchKernelGGL(k_backproject_eq6, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, proj, L.d_views, L.adj,
+                       fbase, kappa, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cbct_hip_error(e, "k_backproject_eq6 launch");
+    return CBCT_OK;
+}

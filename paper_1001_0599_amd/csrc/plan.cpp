@@ -305,3 +305,11 @@ extern "C" cbct_status cbct_forward_columns(const cbct_plan *p, int level, const
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: volume must be 16-byte aligned");
     return cbct_launch_forward(p->lv[level], d_vol_cols, nullptr, d_proj, nullptr, (hipStream_t)stream);
 }
+
+extern "C" cbct_status cbct_backproject_eq6(const cbct_plan *p, int level, const float *d_proj, float *d_vol,
+                                            cbct_stream_t stream) {
+    cbct_status s = check_level(p, level, "backproject_eq6");
+    if (s) return s;
+    if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "backproject_eq6: NULL pointer");
+    return cbct_launch_backproject_eq6(p->lv[level], d_proj, nullptr, 0.0f, d_vol, (hipStream_t)stream);
+}

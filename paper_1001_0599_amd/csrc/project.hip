@@ -54,7 +54,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int KC, int NPT, bool VEC>
 __global__ void __launch_bounds__(256)
     k_forward(const float *__restrict__ vol_t, const ColParams *__restrict__ cols, int nx, int ny, int nz, int nu,
-              int nv, float pv, int pad, int tw, const float *__restrict__ ysub, float *__restrict__ out,
+              int nv, float pv, int pad, int tw, const float *__restrict__ ysub, int wres, float *__restrict__ out,
               double *__restrict__ partials) {
     extern __shared__ float lds[];
     constexpr int kc = KC;
@@ -182,13 +182,15 @@ __global__ void __launch_bounds__(256)
             const long o1 = ((long)view * nv + j) * nu + i, o2 = ((long)view * nv + jm) * nu + i;
             float r1 = w * acc_t[p], r2 = w * acc_r[p];
             if (ysub) {
-                // residual mode: sum (P f - Y)^2, and hand the adjoint w * (P f - Y)
+                // residual mode: sum (P f - Y)^2, and hand the adjoint w * (P f - Y) (or P f - Y)
                 r1 -= ysub[o1];
                 r2 -= ysub[o2];
                 part += (double)r1 * (double)r1;
                 if (jm != j) part += (double)r2 * (double)r2;
-                r1 *= w;
-                r2 *= w;
+                if (wres) {
+                    r1 *= w;
+                    r2 *= w;
+                }
             }
             out[o1] = r1;
             if (jm != j) out[o2] = r2;
@@ -208,13 +210,13 @@ __global__ void __launch_bounds__(256)
 }
 
 template <int KC, int NPT, bool VEC>
-cbct_status launch_fwd(const Level &L, const float *vol_t, const float *ysub, float *out, double *partials,
+cbct_status launch_fwd(const Level &L, const float *vol_t, const float *ysub, int wres, float *out, double *partials,
                        hipStream_t s, int block) {
     const size_t table = (((size_t)L.fwd_tw * (2 * KC + 1) + 3) & ~(size_t)3) * sizeof(float);
     const size_t lds = table + (size_t)KC * (sizeof(float4) + sizeof(int4));
     dim3 grid(L.nu, L.nviews);
     hipLaunchKernelGGL((k_forward<KC, NPT, VEC>), grid, dim3(block), lds, s, vol_t, L.d_cols, L.nx, L.ny, L.nz,
-                       L.nu, L.nv, (float)L.pv, L.fwd_pad, L.fwd_tw, ysub, out, partials);
+                       L.nu, L.nv, (float)L.pv, L.fwd_pad, L.fwd_tw, ysub, wres, out, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_forward launch");
     return CBCT_OK;
@@ -231,7 +233,8 @@ cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_
 }
 
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *ysub, float *out, double *partials,
-                                hipStream_t s) {
+                                hipStream_t s, bool weight_residual) {
+    const int wres = weight_residual ? 1 : 0;
     const int npairs = (L.nv + 1) / 2;
     int block = ((npairs + 63) / 64) * 64;
     int npt = 1;
@@ -243,8 +246,8 @@ cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float 
         return cbct_set_error(CBCT_ERR_INTERNAL, "forward: chunk %d larger than the work-group %d", L.fwd_kc, block);
     const bool vec = (L.nz % 4) == 0;
 #define CBCT_FWD(KC_, NPT_)                                                                     \
-    return vec ? launch_fwd<KC_, NPT_, true>(L, vol_t, ysub, out, partials, s, block)            \
-               : launch_fwd<KC_, NPT_, false>(L, vol_t, ysub, out, partials, s, block)
+    return vec ? launch_fwd<KC_, NPT_, true>(L, vol_t, ysub, wres, out, partials, s, block)      \
+               : launch_fwd<KC_, NPT_, false>(L, vol_t, ysub, wres, out, partials, s, block)
     if (L.fwd_kc == 32) {
         if (npt == 1) CBCT_FWD(32, 1);
         if (npt == 2) CBCT_FWD(32, 2);

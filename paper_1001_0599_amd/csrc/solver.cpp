@@ -317,16 +317,21 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         for (int k = 0; k <= pr->iters[l]; k++) {
             const bool last = (k == pr->iters[l]);
             if (last && !want_energy) break;
-            // residual r = P f - Y_l and its sum of squares
-            if ((st = cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s))) return st;
+            // residual r = P f - Y_l (ray-weighted for the exact adjoint) and its sum of squares
+            const bool eq6 = pr->step1_eq6 != 0;
+            if ((st = cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s, !eq6))) return st;
             if (want_energy) {
                 if ((st = cbct_launch_sum_rows(b.part, L.nviews * L.nu, 1, b.eng + 2 * eslot, s))) return st;
                 if ((st = cbct_launch_tv_energy(L, pr->tv_eps, b.f, b.part, b.eng + 2 * eslot + 1, s))) return st;
                 eslot++;
             }
             if (last) break;
-            // Step 1
-            if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true))) return st;
+            // Step 1: g = f - kappa P^T r, or with the Eq. 6 backprojector in place of P^T
+            if (eq6) {
+                if ((st = cbct_launch_backproject_eq6(L, b.r, b.f, kappa, b.g, s))) return st;
+            } else if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true))) {
+                return st;
+            }
             // Step 2
             if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
             // Step 3

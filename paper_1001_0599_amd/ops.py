@@ -124,6 +124,15 @@ class Plan:
                                  workspace.numel() * workspace.element_size(), _stream_handle(self.device)))
         return out
 
+    def backproject_eq6(self, y: torch.Tensor, level: int = 0, out: torch.Tensor = None):
+        """The paper's Eq. 6 voxel-driven backprojector (cbct_backproject_eq6)."""
+        _require(y, self.proj_shape(level), "y", self.device)
+        if out is None:
+            out = torch.empty(self.vol_shape(level), dtype=torch.float32, device=self.device)
+        _require(out, self.vol_shape(level), "out", self.device)
+        check(lib().cbct_backproject_eq6(self._h, level, y.data_ptr(), out.data_ptr(), _stream_handle(self.device)))
+        return out
+
     # ---- solver ----------------------------------------------------------------------------
     @staticmethod
     def solve_params(lam=0.05, iters=(20,), levels=None, step=0.0, replay=None, **kw):

@@ -66,6 +66,19 @@ def test_adjoint_matches_oracle(name):
         assert e < TOL, (name, kind, e)
 
 
+@pytest.mark.parametrize("name", ["cube32", "ragged", "anisotropic", "many_columns", "tiny", "batch128_one"])
+def test_backproject_eq6_matches_oracle(name):
+    """The paper's Eq. 6 backprojector against the oracle's (bilinear detector sampling, L^3/(L0 l^2))."""
+    g = CASES[name]
+    announce("eq6 backprojector %s %s" % (name, g.proj_shape))
+    plan = _plan(g)
+    y = S.random_projections(g, 8)
+    got = to_np(plan.backproject_eq6(to_gpu(y)))
+    want = O.backproject_eq6(g, y)
+    e = rel_l2(got, want)
+    assert e < TOL, (name, e)
+
+
 @pytest.mark.parametrize("name", ["cube32", "ragged", "batch128_one"])
 def test_gpu_adjoint_identity(name):
     g = CASES[name]

@@ -81,11 +81,11 @@ def test_rof_alone_matches_oracle():
         assert rel_l2(to_np(u), res.f) < 1e-5, t
 
 
-def _compare_solve(g, Y, lam, iters, levels, step=0.0):
+def _compare_solve(g, Y, lam, iters, levels, step=0.0, **kw):
     """Run oracle and GPU; compare decision traces and volumes (replaying on a tie)."""
-    res = O.reconstruct(g, Y, lam, iters, levels, step=step)
+    res = O.reconstruct(g, Y, lam, iters, levels, step=step, **kw)
     plan = _plan(g, levels)
-    f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True)
+    f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True, **kw)
     got = to_np(f)
     q = _first_divergence(st["trace"], res.trace)
     replayed = False
@@ -98,7 +98,7 @@ def _compare_solve(g, Y, lam, iters, levels, step=0.0):
         stop = abs(abs(enew - e0) / e0 - 1e-3) / 1e-3
         assert min(armijo, stop) < 1e-4, ("decision diverged with a large margin", q, st["trace"][q], res.trace[q])
         f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True,
-                                 replay=[int(r[3]) for r in res.trace])
+                                 replay=[int(r[3]) for r in res.trace], **kw)
         got = to_np(f)
         replayed = True
     e = rel_l2(got, res.f)
@@ -114,6 +114,15 @@ def test_reconstruct_cube32_matches_oracle():
     assert abs(st["t_used"][0] - res.t_used[0]) / res.t_used[0] < 1e-5
     assert rel_l2(st["energy"], res.energy) < 1e-4
     assert np.all(np.diff(st["energy"]) <= 1e-6 * st["energy"][:-1])
+
+
+def test_reconstruct_eq6_step1_matches_oracle():
+    """Algorithm A1 with the paper's Eq. 6 backprojector in Step 1 (in place of the exact P^T)."""
+    announce("reconstruct 32^3, 16 views, 20 iterations, Eq. 6 Step 1")
+    Y = _cube32_y()
+    e, replayed, res, st = _compare_solve(G1, Y, 0.05, [20], 1, step1_eq6=True)
+    assert e < 1e-3, (e, replayed)
+    assert rel_l2(st["energy"], res.energy) < 1e-4
 
 
 @pytest.mark.parametrize("lam", [0.02, 0.05, 0.1])
