@@ -31,7 +31,7 @@ __all__ = [
     "Geometry", "Ellipsoid", "config_geometry", "CONFIGS", "view_angles",
     "make_phantom", "analytic_projections", "voxelize", "poisson_log",
     "random_volume", "random_projections", "serving_requests", "ray_endpoints",
-    "level_geometry",
+    "level_geometry", "short_scan_angles", "mas_to_i0",
 ]
 
 
@@ -93,6 +93,32 @@ def level_geometry(g: Geometry, level: int, bin_detector: bool = True) -> Geomet
 
 
 # --------------------------------------------------------------------------------------
+# Short-scan acquisitions of the paper's physical experiments (Section III.B-C): a few hundred
+# projections over a 200-degree arc (379 for the CatPhan scan, 363 for the head-and-neck and
+# Rando scans), of which an equally spaced subset of 40 is reconstructed, at tube loads from
+# 0.1 to 2.56 mAs per projection.
+# --------------------------------------------------------------------------------------
+def short_scan_angles(n_acquired: int = 363, n_used: int = 40, arc_deg: float = 200.0,
+                      start_deg: float = 0.0) -> tuple:
+    """Angles (radians) of an equally spaced subset of n_used among n_acquired projections spread
+    evenly over [start, start + arc] (first and last at the arc's ends)."""
+    if not (1 <= n_used <= n_acquired):
+        raise ValueError("need 1 <= n_used <= n_acquired")
+    step = arc_deg / (n_acquired - 1) if n_acquired > 1 else 0.0
+    if n_used == 1:
+        picks = [0]
+    else:
+        picks = [int(round(q * (n_acquired - 1) / (n_used - 1))) for q in range(n_used)]
+    return tuple(math.radians(start_deg + k * step) for k in picks)
+
+
+def mas_to_i0(mas: float, i0_ref: float = 1e5, mas_ref: float = 2.56) -> float:
+    """Incident photons per detector pixel for a tube load (mAs per projection): proportional to
+    the load, I0_ref at mas_ref (the CatPhan protocol)."""
+    return i0_ref * mas / mas_ref
+
+
+# --------------------------------------------------------------------------------------
 # Workloads (sizes from the paper's NCAT experiment scaled to five
 # workload definitions; the phantoms below stand in for NCAT/CatPhan/patient data).
 # --------------------------------------------------------------------------------------
@@ -107,6 +133,11 @@ CONFIGS = {
                  seeds=(11, 32)),
     "batch8x128": dict(geometry=_BATCH128, batch=8, lam=0.05, I0=1e5, phantom_seeds=tuple(range(41, 49)),
                  noise_seed=49, perturb_seed=40, direction_seed=50),
+    # the cube's grid scanned like the physical experiments: 40 of 363 projections over 200 deg,
+    # tube loads from 0.1 to 2.56 mAs per projection
+    "shortscan32": dict(geometry=dataclasses.replace(_CUBE32, n_views=40, angles=short_scan_angles(363, 40, 200.0)),
+                        n_acquired=363, arc_deg=200.0,
+                        mas=(0.1, 0.4, 1.0, 2.56), levels=1, iters=[20], lam=0.05, seeds=(11, 33)),
     "serving_mix": dict(n_requests=256, rate=4.0, vol_types=((64, 64, 64), (128, 128, 128), (256, 256, 96)),
                  h=2.0, views=(20, 120), iters=[30], lam=0.05, I0=1e5, budget_bytes=200 * 10**9,
                  seeds=dict(arrivals=51, mix=52, phantom0=5000, noise0=6000)),

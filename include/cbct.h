@@ -148,6 +148,10 @@ typedef struct {
     int replay_len;
     int step1_eq6;          /* 0 (default): Step 1 uses the exact P^T; 1: the Eq. 6 backprojector
                              * (cbct_backproject_eq6) applied to P f - Y, with the same step */
+    double conv_tol;        /* > 0: "until convergence" per level (Section II.C.3): a level stops at
+                             * the first k >= 1 with |E(f_k) - E(f_k-1)| <= conv_tol E(f_k-1), iters[l]
+                             * being the upper bound (one more stream synchronisation per outer
+                             * iteration); 0 (default): exactly iters[l] iterations */
 } cbct_solve_params;
 
 /* Optional diagnostics; arrays are caller-owned and may be NULL (lengths may exceed capacities:

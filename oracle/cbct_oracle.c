@@ -61,6 +61,8 @@ typedef struct {
     int rof_max_iter;
     int rof_max_backtrack;
     int step1_eq6;        /* 1: Step 1 uses the Eq. 6 backprojector instead of the exact P^T */
+    double conv_tol;      /* > 0: a level stops once |E(f_k) - E(f_k-1)| <= conv_tol E(f_k-1) (k >= 1);
+                           * its iteration count is then the upper bound */
 } og_params;
 
 typedef struct {
@@ -563,10 +565,19 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
     double *u = (double *)malloc(sizeof(double) * (size_t)nvox);
     double kappa = t * og_kappa0(g);
     og_trace_ctx tc = {st, level, 0};
+    double e_prev = 0.0;
+    int converged = 0;
     for (int k = 0; k < iters; k++) {
         /* Step 1: gradient step on the data term, g = f - t N dD/df */
         double Dk = og_data_term(g, f, Y, r);
-        og_energy_push(st, Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps));
+        double Ek = Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps);
+        og_energy_push(st, Ek);
+        /* "until convergence" (Section II.C.3): f_k is final once the energy stalls */
+        if (pr->conv_tol > 0.0 && k >= 1 && fabs(Ek - e_prev) <= pr->conv_tol * e_prev) {
+            converged = 1;
+            break;
+        }
+        e_prev = Ek;
         if (pr->step1_eq6) orc_backproject_eq6(g, r, pt);
         else orc_adjoint(g, r, pt);
         for (long v = 0; v < nvox; v++) gg[v] = (og_fault == 9) ? f[v] + kappa * pt[v] : f[v] - kappa * pt[v];
@@ -576,7 +587,7 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
         /* Step 3: non-negativity */
         for (long v = 0; v < nvox; v++) f[v] = u[v] > 0.0 ? u[v] : 0.0;
     }
-    if (st) {
+    if (st && !converged) {
         double Dk = og_data_term(g, f, Y, r);
         og_energy_push(st, Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps));
     }

@@ -39,7 +39,8 @@ class SolveParams(C.Structure):
     _fields_ = [("lam", C.c_double), ("iters", C.POINTER(C.c_int)), ("levels", C.c_int), ("step", C.c_double),
                 ("tv_eps", C.c_double), ("armijo_c", C.c_double), ("backtrack", C.c_double),
                 ("rof_tol", C.c_double), ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int),
-                ("replay", C.POINTER(C.c_int)), ("replay_len", C.c_int), ("step1_eq6", C.c_int)]
+                ("replay", C.POINTER(C.c_int)), ("replay_len", C.c_int), ("step1_eq6", C.c_int),
+                ("conv_tol", C.c_double)]
 
 
 class SolveStats(C.Structure):

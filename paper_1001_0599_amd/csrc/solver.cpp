@@ -113,6 +113,7 @@ cbct_status check_params(const cbct_plan *p, const cbct_solve_params *pr, const 
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: invalid line-search or TV parameters", who);
     if (pr->replay_len < 0 || (pr->replay_len > 0 && !pr->replay))
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: replay_len > 0 needs a replay array", who);
+    if (!(pr->conv_tol >= 0.0)) return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: conv_tol < 0", who);
     return CBCT_OK;
 }
 
@@ -277,6 +278,8 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
     }
     TraceSink sink{stats};
     const bool want_energy = stats && stats->energy;
+    const bool conv = pr->conv_tol > 0.0;  // the stop rule needs E(f_k) on the host every iteration
+    std::vector<int> slots_of_level(levels, 0);
     int replay_pos = 0;
     int eslot = 0;
     const Level &L0 = p->lv[0];
@@ -314,16 +317,29 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         if (stats) stats->t_used[l] = t;
         const float kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
         if ((st = cbct_launch_to_columns(L, b.f, b.ft, s))) return st;
+        double e_prev = 0.0;
         for (int k = 0; k <= pr->iters[l]; k++) {
             const bool last = (k == pr->iters[l]);
             if (last && !want_energy) break;
             // residual r = P f - Y_l (ray-weighted for the exact adjoint) and its sum of squares
             const bool eq6 = pr->step1_eq6 != 0;
             if ((st = cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s, !eq6))) return st;
-            if (want_energy) {
+            if (want_energy || conv) {
                 if ((st = cbct_launch_sum_rows(b.part, L.nviews * L.nu, 1, b.eng + 2 * eslot, s))) return st;
                 if ((st = cbct_launch_tv_energy(L, pr->tv_eps, b.f, b.part, b.eng + 2 * eslot + 1, s))) return st;
                 eslot++;
+                slots_of_level[l]++;
+            }
+            if (conv) {
+                // "until convergence": f_k is final once the energy stalls
+                double e2[2];
+                CBCT_HIP(hipMemcpyAsync(e2, b.eng + 2 * (eslot - 1), sizeof(e2), hipMemcpyDeviceToHost, s));
+                CBCT_HIP(hipStreamSynchronize(s));
+                const double Ek = e2[0] / (double)L.nray() + pr->lambda * e2[1] / (double)L.nvox();
+                if (!std::isfinite(Ek))
+                    return cbct_set_error(CBCT_ERR_NONFINITE, "energy is not finite (level %d, outer %d)", l, k);
+                if (k >= 1 && std::fabs(Ek - e_prev) <= pr->conv_tol * e_prev) break;
+                e_prev = Ek;
             }
             if (last) break;
             // Step 1: g = f - kappa P^T r, or with the Eq. 6 backprojector in place of P^T
@@ -348,7 +364,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             int idx = 0;
             for (int l = levels - 1; l >= 0; l--) {
                 const Level &L = p->lv[l];
-                for (int k = 0; k <= pr->iters[l]; k++, idx++) {
+                for (int k = 0; k < slots_of_level[l]; k++, idx++) {
                     const double E = e[2 * idx] / (double)L.nray() + pr->lambda * e[2 * idx + 1] / (double)L.nvox();
                     if (stats->energy_len < stats->energy_cap) stats->energy[stats->energy_len] = E;
                     stats->energy_len++;

@@ -30,6 +30,8 @@ CASES = {
     "many_columns": dataclasses.replace(G1, nu=256, pu=0.3, nv=24, n_views=3, angles=(0.3, 2.0, 4.4)),
     # 17 views over few tiles: the gather splits the views into groups, some of them empty
     "view_groups": dataclasses.replace(G1, n_views=17),
+    # 40 of 363 projections over a 200-degree arc (the paper's physical scans)
+    "short_scan": S.config_geometry("shortscan32"),
     "batch128_one": S.config_geometry("batch8x128"),
 }
 

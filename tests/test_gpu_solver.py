@@ -125,6 +125,30 @@ def test_reconstruct_eq6_step1_matches_oracle():
     assert rel_l2(st["energy"], res.energy) < 1e-4
 
 
+@pytest.mark.parametrize("mas", S.CONFIGS["shortscan32"]["mas"])
+def test_reconstruct_short_scan_mas_sweep(mas):
+    """40 of 363 projections over 200 degrees at tube loads from 0.1 to 2.56 mAs per projection."""
+    cfg = S.CONFIGS["shortscan32"]
+    g = cfg["geometry"]
+    announce("reconstruct short scan, 40 views over 200 deg, %g mAs" % mas)
+    ph = S.make_phantom(g, cfg["seeds"][0])
+    Y = S.poisson_log(S.analytic_projections(g, ph), S.mas_to_i0(mas), cfg["seeds"][1])
+    e, replayed, res, st = _compare_solve(g, Y, cfg["lam"], cfg["iters"], cfg["levels"])
+    assert e < 1e-3, (mas, e, replayed)
+
+
+def test_reconstruct_until_convergence_4_levels():
+    """Four levels (the paper's 8h -> h cascade), each run until the energy stalls (relative change
+    <= 1e-2, at most 80 iterations): the same stopping iterations as the oracle and the same volume."""
+    announce("reconstruct low dose, 4 levels until convergence")
+    Y = _cube32_y(I0=2e3, noise_seed=32)
+    e, replayed, res, st = _compare_solve(G1, Y, 0.05, [80, 80, 80, 80], 4, conv_tol=1e-2)
+    outer = lambda tr: sorted({(int(r[0]), int(r[1])) for r in tr})
+    assert outer(st["trace"]) == outer(res.trace)
+    assert len(st["energy"]) == len(res.energy) < 4 * 81
+    assert e < 1e-3, (e, replayed)
+
+
 @pytest.mark.parametrize("lam", [0.02, 0.05, 0.1])
 def test_reconstruct_low_dose_3_levels(lam):
     announce("reconstruct low dose, 3 levels x 100 iterations, lambda %g" % lam)

@@ -143,6 +143,33 @@ def pin_continuum_adjoint():
     return mx < 0.03 and rms < 0.006, (mx, rms)
 
 
+# ------------------------------------------------------------------ "until convergence" per level
+def pin_convergence_rule():
+    """The per-level stop of Section II.C.3: a vanishing tolerance changes nothing (bitwise); a
+    tolerance of 1 stops every level after one iteration; at 3e-3 every level ends at the first
+    energy pair within the tolerance (or at its iteration bound)."""
+    Y = S.poisson_log(S.analytic_projections(G1, S.make_phantom(G1, 11)), 2e3, 32)
+    a = O.reconstruct(G1, Y, 0.05, [4, 4, 4], 3, conv_tol=1e-30)
+    b = O.reconstruct(G1, Y, 0.05, [4, 4, 4], 3)
+    ok1 = np.array_equal(a.f, b.f) and np.array_equal(a.energy, b.energy)
+    c = O.reconstruct(G1, Y, 0.05, [4, 4, 4], 3, conv_tol=1.0)
+    ok2 = len(c.energy) == 6 and sorted({(int(r[0]), int(r[1])) for r in c.trace}) == [(0, 0), (1, 0), (2, 0)]
+    tol, bound = 3e-3, 40
+    d = O.reconstruct(G1, Y, 0.05, [bound] * 3, 3, conv_tol=tol)
+    tr = np.array(d.trace)
+    ok3, pos = True, 0
+    for lvl in (2, 1, 0):
+        n_outer = int(tr[tr[:, 0] == lvl][:, 1].max()) + 1
+        e = d.energy[pos:pos + n_outer + 1]
+        pos += n_outer + 1
+        rel = np.abs(np.diff(e)) / e[:-1]
+        if n_outer < bound:
+            ok3 &= bool(rel[-1] <= tol) and bool(np.all(rel[:-1] > tol))
+        else:
+            ok3 &= bool(np.all(rel > tol))
+    return ok1 and ok2 and ok3, (ok1, ok2, ok3)
+
+
 # ------------------------------------------------------------------ Eq. 6 backprojector pins
 EQ6 = dataclasses.replace(G1, nx=12, ny=10, nz=8, nu=160, nv=128, pu=0.75, pv=0.75, n_views=5,
                           angles=(0.0, 0.7, 2.0, 3.6, 5.1))
@@ -349,7 +376,7 @@ def pin_constants():
 
 PINS = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_chords, pin_mass, pin_box,
         pin_centroid, pin_continuum_adjoint, pin_eq6_affine, pin_eq6_near_adjoint, pin_tv_gradient, pin_tv_closed_forms, pin_transfers,
-        pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants]
+        pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants, pin_convergence_rule]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])

@@ -77,3 +77,15 @@ def test_torch_projections_match_numpy():
     assert np.max(np.abs(a - b)) < 1e-9  # rounding near tangent rays
     y = S.poisson_log_torch(torch.as_tensor(a), 1e5, 1)
     assert torch.isfinite(y).all()
+
+
+def test_short_scan_angles():
+    a = np.degrees(S.short_scan_angles(363, 40, 200.0))
+    assert len(a) == 40 and a[0] == 0.0 and abs(a[-1] - 200.0) < 1e-12
+    step = 200.0 / 362
+    k = a / step
+    assert np.allclose(k, np.round(k), atol=1e-9)          # a subset of the acquired angles
+    assert np.all(np.diff(np.round(k)) >= 9) and np.all(np.diff(np.round(k)) <= 10)  # equally spaced picks
+    assert S.mas_to_i0(2.56) == 1e5 and abs(S.mas_to_i0(0.1) - 1e5 * 0.1 / 2.56) < 1e-9
+    g = S.config_geometry("shortscan32")
+    assert g.n_views == 40 and len(g.angles) == 40
