@@ -294,10 +294,13 @@ constexpr int GS_ROWS32 = 288;
 constexpr int GS_CC = 64;  // detector columns per column chunk (one wave lists them)
 
 struct GsCol {
-    float fx0, dfx, fy0, dfy, idfx, idfy;
-    int ka, kb;  // samples of the column inside the tile box
-    long zrow;   // float offset of sample ka's cells c0.. in the profiles
+    float fx0, dfx, fy0, dfy;  // index coordinates of sample k: (fx0 + k dfx, fy0 + k dfy)
+    float idfx, idfy;          // samples per unit of x (of y); 0 when the column keeps x (y) fixed
+    float hx, hy;              // |idfx| (|idfy|), or unbounded where that axis sets no window
+    int ka, kb;                // samples of the column inside the tile box
+    long zrow;                 // float offset of sample ka's cells c0.. in the profiles
 };
+static_assert(sizeof(GsCol) == 48, "GsCol layout");
 
 // With view groups (vgroups > 1) the work-group of group g covers views [g vper, (g+1) vper) and
 // writes its sums to part[g]; k_adj_combine adds the groups in order.
@@ -367,6 +370,8 @@ __global__ void __launch_bounds__(256)
                     g.dfy = cp.dfy;
                     g.idfx = cp.idfx;
                     g.idfy = cp.idfy;
+                    g.hx = cp.idfx != 0.0f ? fabsf(cp.idfx) : 1e30f;
+                    g.hy = cp.idfy != 0.0f ? fabsf(cp.idfy) : 1e30f;
                     g.ka = ka;
                     g.kb = ka + nr - 1;
                     g.zrow = zi.off + (long)(ka - zi.k0) * A.nz + c0;
@@ -428,18 +433,19 @@ __global__ void __launch_bounds__(256)
                         const int kfirst = max(g.ka, g.ka + R0 - cnt[t]);
                         const int klast = min(g.kb, g.ka + R0 + nrows - 1 - cnt[t]);
                         const float kb0 = (float)(kfirst - 1), kb1 = (float)(klast + 1);
-                        float lo = kb0, hi = kb1;
-                        window4(g.fx0, g.idfx, g.fy0, g.idfy, (float)(a - 1), (float)(a + 1), (float)(b - 1),
-                                (float)(b + 1), lo, hi);
+                        // samples within one voxel of (a, b): |k - kc| < h on each axis, kc the sample
+                        // index at the voxel centre (a window-free axis has kc = 0, h unbounded)
+                        const float fxa = g.fx0 - (float)a, fya = g.fy0 - (float)b;  // sample 0 relative to (a, b)
+                        const float kcx = -fxa * g.idfx, kcy = -fya * g.idfy;
+                        float lo = fmaxf(kcx - g.hx, kcy - g.hy), hi = fminf(kcx + g.hx, kcy + g.hy);
                         lo = fminf(fmaxf(lo, kb0), kb1);
                         hi = fminf(fmaxf(hi, kb0), kb1);
                         const int klo = (int)floorf(lo) + 1, khi = min((int)ceilf(hi) - 1, klast);
                         const int rbase = cnt[t] - R0 - g.ka;  // staged row of sample k: rbase + k
                         for (int k = klo; k <= khi; k++) {
                             const float kf = (float)k;
-                            const float fx = fmaf(kf, g.dfx, g.fx0), fy = fmaf(kf, g.dfy, g.fy0);
-                            const float wxy =
-                                fmaxf(1.0f - fabsf(fx - (float)a), 0.0f) * fmaxf(1.0f - fabsf(fy - (float)b), 0.0f);
+                            const float dx = fmaf(kf, g.dfx, fxa), dy = fmaf(kf, g.dfy, fya);
+                            const float wxy = fmaxf(1.0f - fabsf(dx), 0.0f) * fmaxf(1.0f - fabsf(dy), 0.0f);
                             const float4 *zr = zs + (rbase + k) * GS_PITCH;
 #pragma unroll
                             for (int q = 0; q < GS_Q; q++) {
