@@ -73,6 +73,8 @@ def lib():
             L.orc_adjoint.argtypes = [P(Geom), _D, _D]
             L.orc_adjoint_voxels.argtypes = [P(Geom), _D, C.c_long, _L, _D]
             L.orc_backproject_eq6.argtypes = [P(Geom), _D, _D]
+            L.orc_forward_siddon.argtypes = [P(Geom), _D, _D]
+            L.orc_adjoint_siddon.argtypes = [P(Geom), _D, _D]
             L.orc_tv_energy.argtypes = [P(Geom), _D, C.c_double]
             L.orc_tv_energy.restype = C.c_double
             L.orc_tv_grad.argtypes = [P(Geom), _D, C.c_double, _D]
@@ -157,6 +159,24 @@ def adjoint(g, y) -> np.ndarray:
     y = _f64(y).reshape(h.proj_shape)
     f = np.empty(h.vol_shape)
     lib().orc_adjoint(h.ref(), _ptr(y), _ptr(f))
+    return f
+
+
+def forward_siddon(g, f) -> np.ndarray:
+    """Siddon's exact radiological path through the piecewise-constant volume."""
+    h = _GeomHolder(g)
+    f = _f64(f).reshape(h.vol_shape)
+    y = np.empty(h.proj_shape)
+    lib().orc_forward_siddon(h.ref(), _ptr(f), _ptr(y))
+    return y
+
+
+def adjoint_siddon(g, y) -> np.ndarray:
+    """Transpose of forward_siddon by the scatter loop."""
+    h = _GeomHolder(g)
+    y = _f64(y).reshape(h.proj_shape)
+    f = np.empty(h.vol_shape)
+    lib().orc_adjoint_siddon(h.ref(), _ptr(y), _ptr(f))
     return f
 
 

@@ -28,6 +28,12 @@
  *   - Step 2 (ROF) by gradient descent with the Armijo rule of Eq. (5), c = 0.01,
  *     alpha = 0.6, eps = 0.1 %, initial step t, at most 50 iterations and 30
  *     backtracks, started from u = g.
+ *   - Siddon's ray tracing (Section II.C.2; also the paper's data simulator, Section III.A)
+ *     as an alternative P: each voxel is constant on its cube, and a ray's value is the sum
+ *     over voxels of (length of S->D inside the cube) x voxel value.  The pieces come from the
+ *     sorted parameters at which the segment crosses the grid planes; a piece's voxel is the
+ *     one holding its midpoint (cubes half-open on their upper faces: a ray in a face plane
+ *     belongs to the cube above it).  Its transpose is the exact matrix transpose.
  *   - Multigrid (Section II.C.3): coarse-to-fine levels, dims halved per level
  *     over the same box, detector binned 2x2 per level, cell-centred trilinear
  *     prolongation (3/4, 1/4 per axis, clamped), restriction = (1/8) Prol^T.
@@ -227,6 +233,126 @@ void orc_forward(const og_geom *g, const double *f, double *y) {
         int view = (int)(r / ((long)g->nu * g->nv));
         y[r] = og_ray_integral(g, f, view, i, j);
     }
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* Siddon's exact radiological path (the paper's projector and data simulator,        */
+/* Section II.C.2): the ray integral of the piecewise-constant volume, i.e. the sum    */
+/* over voxels of the ray's length inside the voxel's cube times the voxel's value.    */
+/* The plain method: every parameter alpha in (0, 1) where the segment S->D crosses a  */
+/* grid plane, sorted; each piece between consecutive parameters lies in the voxel     */
+/* that contains its midpoint.                                                         */
+/* ---------------------------------------------------------------------------------- */
+static void og_ray_ends(const og_geom *g, int view, int i, int j, double S[3], double D[3]) {
+    double th = og_angle(g, view);
+    double ew[3] = {cos(th), sin(th), 0.0}, eu[3] = {sin(th), -cos(th), 0.0};
+    double u = (i - 0.5 * (g->nu - 1)) * g->pu, v = (j - 0.5 * (g->nv - 1)) * g->pv;
+    for (int q = 0; q < 3; q++) {
+        S[q] = -g->sad * ew[q];
+        D[q] = S[q] + g->sdd * ew[q] + u * eu[q] + (q == 2 ? v : 0.0);
+    }
+}
+
+static int og_cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* the ray's pieces: alpha breakpoints (sorted, 0 and 1 included) into buf, count returned */
+static int og_siddon_alphas(const og_geom *g, const double S[3], const double D[3], double *buf) {
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double h[3] = {g->hx, g->hy, g->hz};
+    int m = 0;
+    buf[m++] = 0.0;
+    buf[m++] = 1.0;
+    for (int q = 0; q < 3; q++) {
+        double dq = D[q] - S[q];
+        if (dq == 0.0 || (og_fault == 13 && q == 2)) continue;
+        for (int p = 0; p <= n[q]; p++) {
+            double plane = (p - 0.5 * n[q]) * h[q];
+            double a = (plane - S[q]) / dq;
+            if (a > 0.0 && a < 1.0) buf[m++] = a;
+        }
+    }
+    qsort(buf, (size_t)m, sizeof(double), og_cmp_double);
+    return m;
+}
+
+/* flat index of the voxel containing point p, or -1 outside the grid */
+static long og_voxel_at(const og_geom *g, const double p[3]) {
+    int a = (int)floor(p[0] / g->hx + 0.5 * g->nx);
+    int b = (int)floor(p[1] / g->hy + 0.5 * g->ny);
+    int c = (int)floor(p[2] / g->hz + 0.5 * g->nz);
+    if (a < 0 || a >= g->nx || b < 0 || b >= g->ny || c < 0 || c >= g->nz) return -1;
+    return ((long)c * g->ny + b) * g->nx + a;
+}
+
+void orc_forward_siddon(const og_geom *g, const double *f, double *y) {
+    long nray = og_nray(g);
+    int cap = g->nx + g->ny + g->nz + 8;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)cap);
+#pragma omp for schedule(dynamic, 64)
+        for (long r = 0; r < nray; r++) {
+            int i = (int)(r % g->nu), j = (int)((r / g->nu) % g->nv), view = (int)(r / ((long)g->nu * g->nv));
+            double S[3], D[3];
+            og_ray_ends(g, view, i, j, S, D);
+            double len = sqrt((D[0] - S[0]) * (D[0] - S[0]) + (D[1] - S[1]) * (D[1] - S[1]) + (D[2] - S[2]) * (D[2] - S[2]));
+            int m = og_siddon_alphas(g, S, D, buf);
+            double acc = 0.0;
+            for (int k = 0; k + 1 < m; k++) {
+                if (buf[k + 1] <= buf[k]) continue;
+                double am = 0.5 * (buf[k] + buf[k + 1]), p[3];
+                for (int q = 0; q < 3; q++) p[q] = S[q] + am * (D[q] - S[q]);
+                long v = og_voxel_at(g, p);
+                if (v >= 0) acc += (buf[k + 1] - buf[k]) * len * f[v];
+            }
+            y[r] = acc;
+        }
+        free(buf);
+    }
+}
+
+/* transpose of orc_forward_siddon (scatter into per-thread volumes, summed in thread order) */
+void orc_adjoint_siddon(const og_geom *g, const double *y, double *f) {
+    long nvox = og_nvox(g), nray = og_nray(g);
+    int nt = orc_get_threads(), cap = g->nx + g->ny + g->nz + 8;
+    double **vols = (double **)calloc((size_t)nt, sizeof(double *));
+    for (int t = 0; t < nt; t++) vols[t] = (double *)calloc((size_t)nvox, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = vols[tid];
+        double *buf = (double *)malloc(sizeof(double) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (long r = 0; r < nray; r++) {
+            if (y[r] == 0.0) continue;
+            int i = (int)(r % g->nu), j = (int)((r / g->nu) % g->nv), view = (int)(r / ((long)g->nu * g->nv));
+            double S[3], D[3];
+            og_ray_ends(g, view, i, j, S, D);
+            double len = sqrt((D[0] - S[0]) * (D[0] - S[0]) + (D[1] - S[1]) * (D[1] - S[1]) + (D[2] - S[2]) * (D[2] - S[2]));
+            int m = og_siddon_alphas(g, S, D, buf);
+            for (int k = 0; k + 1 < m; k++) {
+                if (buf[k + 1] <= buf[k]) continue;
+                double am = 0.5 * (buf[k] + buf[k + 1]), p[3];
+                for (int q = 0; q < 3; q++) p[q] = S[q] + am * (D[q] - S[q]);
+                long v = og_voxel_at(g, p);
+                if (v >= 0) acc[v] += (buf[k + 1] - buf[k]) * len * y[r];
+            }
+        }
+        free(buf);
+    }
+    for (long v = 0; v < nvox; v++) {
+        double s = 0.0;
+        for (int t = 0; t < nt; t++) s += vols[t][v];
+        f[v] = s;
+    }
+    for (int t = 0; t < nt; t++) free(vols[t]);
+    free(vols);
 }
 
 /* P at selected rays (flat indices view*nv*nu + j*nu + i) */

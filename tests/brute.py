@@ -106,3 +106,37 @@ def box_chords(g, half_extent):
         hi = np.where(dq == 0, np.where(inside, np.inf, -np.inf), hi)
         t0, t1 = np.maximum(t0, lo), np.minimum(t1, hi)
     return np.maximum(t1 - t0, 0.0) * np.linalg.norm(d, axis=-1)
+
+
+def cube_lengths(g):
+    """Dense matrix of ray-in-voxel lengths: A[ray, voxel] = length of the segment S->D inside
+    the voxel's cube [x_a - hx/2, x_a + hx/2] x ..., by clipping the segment against the cube's
+    three slabs (a route independent of the oracle's sorted plane crossings).  A ray lying in a
+    face plane belongs to the cube on the face's upper side (half-open slabs)."""
+    import cbct_synth
+    S, D = cbct_synth.ray_endpoints(g)
+    d = (D - S[:, None, None, :]).reshape(-1, 3)
+    Sr = np.repeat(S, g.nv * g.nu, axis=0)
+    length = np.linalg.norm(d, axis=1)
+    xs = (np.arange(g.nx) - (g.nx - 1) / 2) * g.hx
+    ys = (np.arange(g.ny) - (g.ny - 1) / 2) * g.hy
+    zs = (np.arange(g.nz) - (g.nz - 1) / 2) * g.hz
+    A = np.zeros((len(d), g.n_vox))
+    h = (g.hx, g.hy, g.hz)
+    for c, zc in enumerate(zs):
+        for b, yc in enumerate(ys):
+            for a, xc in enumerate(xs):
+                t0 = np.zeros(len(d))
+                t1 = np.ones(len(d))
+                for q, cen in enumerate((xc, yc, zc)):
+                    lo, hi = cen - h[q] / 2, cen + h[q] / 2
+                    dq, oq = d[:, q], Sr[:, q]
+                    par = dq == 0
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        ta, tb = (lo - oq) / dq, (hi - oq) / dq
+                    lo_t = np.where(par, np.where((oq >= lo) & (oq < hi), -np.inf, np.inf), np.minimum(ta, tb))
+                    hi_t = np.where(par, np.where((oq >= lo) & (oq < hi), np.inf, -np.inf), np.maximum(ta, tb))
+                    t0, t1 = np.maximum(t0, lo_t), np.minimum(t1, hi_t)
+                A[:, (c * g.ny + b) * g.nx + a] = np.maximum(t1 - t0, 0.0) * length
+    return A
+
