@@ -107,6 +107,23 @@ cbct_status cbct_forward_columns(const cbct_plan *plan, int level, const float *
 cbct_status cbct_backproject_eq6(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
                                  cbct_stream_t stream);
 
+/* Siddon's exact radiological path (the ray tracer of Section II.C.2 and the data simulator of
+ * Section III.A) as an alternative projector: each voxel is constant on its cube (half-open on the
+ * upper faces) and d_proj = P_s d_vol holds, per ray S -> D, the sum over voxels of the length of
+ * S -> D inside the cube times the voxel value.  d_vol [nz][ny][nx], d_proj [n_views][nv][nu] at
+ * `level`, device memory; d_ws of at least cbct_forward_workspace_size bytes (the same column-major
+ * copy of the volume as cbct_forward).  INVALID_ARG on NULL pointers, a bad level or a small
+ * workspace. */
+cbct_status cbct_forward_siddon(const cbct_plan *plan, int level, const float *d_vol, float *d_proj, void *d_ws,
+                                size_t ws_bytes, cbct_stream_t stream);
+
+/* Transpose of cbct_forward_siddon: d_vol = P_s^T d_proj (the matched backprojector; Section
+ * II.C.2 explains why it is voxel-driven): each voxel gathers length x value over the rays that
+ * cross its cube; every voxel of d_vol is written once, no atomics, no workspace.  Errors as
+ * cbct_forward_siddon. */
+cbct_status cbct_adjoint_siddon(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
+                                cbct_stream_t stream);
+
 /* Workspace (device bytes) of cbct_adjoint at `level`: the z profiles of every detector
  * column's samples (views x columns x samples in the grid's support x nz floats). */
 cbct_status cbct_adjoint_workspace_size(const cbct_plan *plan, int level, size_t *bytes);

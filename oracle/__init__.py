@@ -75,6 +75,8 @@ def lib():
             L.orc_backproject_eq6.argtypes = [P(Geom), _D, _D]
             L.orc_forward_siddon.argtypes = [P(Geom), _D, _D]
             L.orc_adjoint_siddon.argtypes = [P(Geom), _D, _D]
+            L.orc_forward_siddon_rays.argtypes = [P(Geom), _D, C.c_long, _L, _D]
+            L.orc_adjoint_siddon_voxels.argtypes = [P(Geom), _D, C.c_long, _L, _D]
             L.orc_tv_energy.argtypes = [P(Geom), _D, C.c_double]
             L.orc_tv_energy.restype = C.c_double
             L.orc_tv_grad.argtypes = [P(Geom), _D, C.c_double, _D]
@@ -178,6 +180,27 @@ def adjoint_siddon(g, y) -> np.ndarray:
     f = np.empty(h.vol_shape)
     lib().orc_adjoint_siddon(h.ref(), _ptr(y), _ptr(f))
     return f
+
+
+def forward_siddon_rays(g, f, rays) -> np.ndarray:
+    """forward_siddon at selected flat ray indices."""
+    h = _GeomHolder(g)
+    f = _f64(f).reshape(h.vol_shape)
+    rays = np.ascontiguousarray(rays, dtype=np.int64)
+    out = np.empty(len(rays))
+    lib().orc_forward_siddon_rays(h.ref(), _ptr(f), len(rays), rays.ctypes.data_as(_L), _ptr(out))
+    return out
+
+
+def adjoint_siddon_voxels(g, y, voxels) -> np.ndarray:
+    """adjoint_siddon at selected flat voxel indices, each from its cube's chords with the rays
+    whose pixels lie in the cube's projected bounding box."""
+    h = _GeomHolder(g)
+    y = _f64(y).reshape(h.proj_shape)
+    voxels = np.ascontiguousarray(voxels, dtype=np.int64)
+    out = np.empty(len(voxels))
+    lib().orc_adjoint_siddon_voxels(h.ref(), _ptr(y), len(voxels), voxels.ctypes.data_as(_L), _ptr(out))
+    return out
 
 
 def backproject_eq6(g, T) -> np.ndarray:

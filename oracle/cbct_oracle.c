@@ -287,6 +287,24 @@ static long og_voxel_at(const og_geom *g, const double p[3]) {
     return ((long)c * g->ny + b) * g->nx + a;
 }
 
+/* Siddon value of ray r (flat index view*nv*nu + j*nu + i); buf holds nx+ny+nz+8 doubles */
+static double og_siddon_ray(const og_geom *g, const double *f, long r, double *buf) {
+    int i = (int)(r % g->nu), j = (int)((r / g->nu) % g->nv), view = (int)(r / ((long)g->nu * g->nv));
+    double S[3], D[3];
+    og_ray_ends(g, view, i, j, S, D);
+    double len = sqrt((D[0] - S[0]) * (D[0] - S[0]) + (D[1] - S[1]) * (D[1] - S[1]) + (D[2] - S[2]) * (D[2] - S[2]));
+    int m = og_siddon_alphas(g, S, D, buf);
+    double acc = 0.0;
+    for (int k = 0; k + 1 < m; k++) {
+        if (buf[k + 1] <= buf[k]) continue;
+        double am = 0.5 * (buf[k] + buf[k + 1]), p[3];
+        for (int q = 0; q < 3; q++) p[q] = S[q] + am * (D[q] - S[q]);
+        long v = og_voxel_at(g, p);
+        if (v >= 0) acc += (buf[k + 1] - buf[k]) * len * f[v];
+    }
+    return acc;
+}
+
 void orc_forward_siddon(const og_geom *g, const double *f, double *y) {
     long nray = og_nray(g);
     int cap = g->nx + g->ny + g->nz + 8;
@@ -294,23 +312,81 @@ void orc_forward_siddon(const og_geom *g, const double *f, double *y) {
     {
         double *buf = (double *)malloc(sizeof(double) * (size_t)cap);
 #pragma omp for schedule(dynamic, 64)
-        for (long r = 0; r < nray; r++) {
-            int i = (int)(r % g->nu), j = (int)((r / g->nu) % g->nv), view = (int)(r / ((long)g->nu * g->nv));
-            double S[3], D[3];
-            og_ray_ends(g, view, i, j, S, D);
-            double len = sqrt((D[0] - S[0]) * (D[0] - S[0]) + (D[1] - S[1]) * (D[1] - S[1]) + (D[2] - S[2]) * (D[2] - S[2]));
-            int m = og_siddon_alphas(g, S, D, buf);
-            double acc = 0.0;
-            for (int k = 0; k + 1 < m; k++) {
-                if (buf[k + 1] <= buf[k]) continue;
-                double am = 0.5 * (buf[k] + buf[k + 1]), p[3];
-                for (int q = 0; q < 3; q++) p[q] = S[q] + am * (D[q] - S[q]);
-                long v = og_voxel_at(g, p);
-                if (v >= 0) acc += (buf[k + 1] - buf[k]) * len * f[v];
-            }
-            y[r] = acc;
-        }
+        for (long r = 0; r < nray; r++) y[r] = og_siddon_ray(g, f, r, buf);
         free(buf);
+    }
+}
+
+/* Siddon P at selected rays */
+void orc_forward_siddon_rays(const og_geom *g, const double *f, long n, const long *rays, double *out) {
+    int cap = g->nx + g->ny + g->nz + 8;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)cap);
+#pragma omp for schedule(dynamic, 16)
+        for (long s = 0; s < n; s++) out[s] = og_siddon_ray(g, f, rays[s], buf);
+        free(buf);
+    }
+}
+
+/* Length of segment S -> D inside the box [lo, hi) (slab clipping; a segment running parallel to
+ * a slab counts when its coordinate lies in [lo, hi)) */
+static double og_box_chord(const double S[3], const double D[3], const double lo[3], const double hi[3]) {
+    double t0 = 0.0, t1 = 1.0;
+    for (int q = 0; q < 3; q++) {
+        double d = D[q] - S[q];
+        if (d == 0.0) {
+            if (S[q] < lo[q] || S[q] >= hi[q]) return 0.0;
+            continue;
+        }
+        double a = (lo[q] - S[q]) / d, b = (hi[q] - S[q]) / d;
+        if (a > b) { double t = a; a = b; b = t; }
+        if (a > t0) t0 = a;
+        if (b < t1) t1 = b;
+    }
+    if (t1 <= t0) return 0.0;
+    double len = sqrt((D[0] - S[0]) * (D[0] - S[0]) + (D[1] - S[1]) * (D[1] - S[1]) + (D[2] - S[2]) * (D[2] - S[2]));
+    return (t1 - t0) * len;
+}
+
+/* (P_s^T y) at selected voxels: the sum over rays of (ray's length inside the voxel's cube) x y,
+ * over the rays of each view whose pixel lies in the cube's projected bounding box */
+void orc_adjoint_siddon_voxels(const og_geom *g, const double *y, long n, const long *vox, double *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long s = 0; s < n; s++) {
+        long idx = vox[s];
+        int a = (int)(idx % g->nx), b = (int)((idx / g->nx) % g->ny), c = (int)(idx / ((long)g->nx * g->ny));
+        double lo[3] = {(a - 0.5 * g->nx) * g->hx, (b - 0.5 * g->ny) * g->hy, (c - 0.5 * g->nz) * g->hz};
+        double hi[3] = {lo[0] + g->hx, lo[1] + g->hy, lo[2] + g->hz};
+        double acc = 0.0;
+        for (int view = 0; view < g->nviews; view++) {
+            double th = og_angle(g, view);
+            double ew[3] = {cos(th), sin(th), 0.0}, eu[3] = {sin(th), -cos(th), 0.0};
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int corner = 0; corner < 8; corner++) {
+                double P[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1], (corner & 4) ? hi[2] : lo[2]};
+                double depth = (P[0] + g->sad * ew[0]) * ew[0] + (P[1] + g->sad * ew[1]) * ew[1];
+                double uu = g->sdd * ((P[0] + g->sad * ew[0]) * eu[0] + (P[1] + g->sad * ew[1]) * eu[1]) / depth;
+                double vv = g->sdd * P[2] / depth;
+                if (uu < umin) umin = uu;
+                if (uu > umax) umax = uu;
+                if (vv < vmin) vmin = vv;
+                if (vv > vmax) vmax = vv;
+            }
+            int i0 = (int)floor(umin / g->pu + 0.5 * (g->nu - 1)) - 1, i1 = (int)ceil(umax / g->pu + 0.5 * (g->nu - 1)) + 1;
+            int j0 = (int)floor(vmin / g->pv + 0.5 * (g->nv - 1)) - 1, j1 = (int)ceil(vmax / g->pv + 0.5 * (g->nv - 1)) + 1;
+            if (i0 < 0) i0 = 0;
+            if (j0 < 0) j0 = 0;
+            if (i1 > g->nu - 1) i1 = g->nu - 1;
+            if (j1 > g->nv - 1) j1 = g->nv - 1;
+            for (int j = j0; j <= j1; j++)
+                for (int i = i0; i <= i1; i++) {
+                    double S[3], D[3];
+                    og_ray_ends(g, view, i, j, S, D);
+                    acc += og_box_chord(S, D, lo, hi) * y[((long)view * g->nv + j) * g->nu + i];
+                }
+        }
+        out[s] = acc;
     }
 }
 

@@ -28,6 +28,19 @@ struct ViewParams {
     float pad0, pad1;
 };
 
+// Per (view, detector column) line of the Siddon projector pair, prepared in FP64 on the host.
+// tau is the transverse distance along the column's xy line from C, its closest approach to the
+// rotation axis: the line is (cx, cy) + tau (ex, ey); the source lies at tau = -t0 and the
+// detector at tau = lxy - t0 (lxy = |D - S|_xy).
+struct SidCol {
+    float cx, cy;    // C (mm)
+    float ex, ey;    // unit direction, source to detector
+    float iex, iey;  // 1/ex, 1/ey (0 when |e| <= 1e-12: the line runs parallel to those planes)
+    float t0, lxy, ilxy;
+    float pad[3];
+};
+static_assert(sizeof(SidCol) == 48, "SidCol layout");
+
 // Tiling of the adjoint gather.
 constexpr int ADJ_TX = 16;     // voxel columns per tile in x (lanes)
 constexpr int ADJ_TY = 16;     // voxel columns per tile in y (lanes)
@@ -80,6 +93,7 @@ struct Level {
     // device tables
     ColParams *d_cols = nullptr;   // [nviews][nu]
     ViewParams *d_views = nullptr; // [nviews]
+    SidCol *d_sid = nullptr;       // [nviews][nu]
     long nvox() const { return (long)nx * ny * nz; }
     long nray() const { return (long)nviews * nv * nu; }
 };
@@ -113,6 +127,9 @@ cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const
 // out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
                                 float *out, float *Zws, hipStream_t s, bool preweighted = false);
+// Siddon pair: out = P_s vol_t (vol_t in the column-major layout) and out = P_s^T proj.
+cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float *out, hipStream_t s);
+cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, hipStream_t s);
 
 // ---- solver pieces --------------------------------------------------------------------------
 constexpr int CBCT_RED_BLOCKS = 8192;  // work-groups of the fixed-size reduction grids

@@ -84,6 +84,7 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
         L.angles[v] = g->angles ? g->angles[v] : 2.0 * M_PI * (double)v / (double)L.nviews;
 
     std::vector<ColParams> cols((size_t)L.nviews * L.nu);
+    std::vector<SidCol> sid((size_t)L.nviews * L.nu);
     std::vector<ViewParams> views(L.nviews);
     double smax = 0.0;
     for (int v = 0; v < L.nviews; v++) {
@@ -99,6 +100,17 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
             const double cx = L.sad / r2 * (L.sdd * u * sn - u * u * cs);
             const double cy = L.sad / r2 * (-L.sdd * u * cs - u * u * sn);
             const double tau_c = L.sad * L.sdd / r;
+            SidCol &sc = sid[(size_t)v * L.nu + i];
+            sc = SidCol{};
+            sc.cx = (float)cx;
+            sc.cy = (float)cy;
+            sc.ex = (float)mx;
+            sc.ey = (float)my;
+            sc.iex = std::fabs(mx) > 1e-12 ? (float)(1.0 / mx) : 0.0f;
+            sc.iey = std::fabs(my) > 1e-12 ? (float)(1.0 / my) : 0.0f;
+            sc.t0 = (float)tau_c;
+            sc.lxy = (float)r;
+            sc.ilxy = (float)(1.0 / r);
             ColParams &c = cols[(size_t)v * L.nu + i];
             const double fx0 = cx / L.hx + 0.5 * (L.nx - 1), fy0 = cy / L.hy + 0.5 * (L.ny - 1);
             const double dfx = L.dtau * mx / L.hx, dfy = L.dtau * my / L.hy;
@@ -173,6 +185,8 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     CBCT_HIP(hipMalloc((void **)&L.d_views, sizeof(ViewParams) * views.size()));
     CBCT_HIP(hipMemcpy(L.d_cols, cols.data(), sizeof(ColParams) * cols.size(), hipMemcpyHostToDevice));
     CBCT_HIP(hipMemcpy(L.d_views, views.data(), sizeof(ViewParams) * views.size(), hipMemcpyHostToDevice));
+    CBCT_HIP(hipMalloc((void **)&L.d_sid, sizeof(SidCol) * sid.size()));
+    CBCT_HIP(hipMemcpy(L.d_sid, sid.data(), sizeof(SidCol) * sid.size(), hipMemcpyHostToDevice));
     CBCT_HIP(hipMalloc((void **)&L.d_zix, sizeof(ZIndex) * zix.size()));
     CBCT_HIP(hipMemcpy(L.d_zix, zix.data(), sizeof(ZIndex) * zix.size(), hipMemcpyHostToDevice));
     return CBCT_OK;
@@ -224,6 +238,7 @@ extern "C" void cbct_plan_destroy(cbct_plan *p) {
         if (L.d_cols) hipFree(L.d_cols);
         if (L.d_views) hipFree(L.d_views);
         if (L.d_zix) hipFree(L.d_zix);
+        if (L.d_sid) hipFree(L.d_sid);
     }
     delete p;
 }
@@ -304,6 +319,29 @@ extern "C" cbct_status cbct_forward_columns(const cbct_plan *p, int level, const
     if (((uintptr_t)d_vol_cols & 15) != 0)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: volume must be 16-byte aligned");
     return cbct_launch_forward(p->lv[level], d_vol_cols, nullptr, d_proj, nullptr, (hipStream_t)stream);
+}
+
+extern "C" cbct_status cbct_forward_siddon(const cbct_plan *p, int level, const float *d_vol, float *d_proj,
+                                           void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
+    cbct_status s = check_level(p, level, "forward_siddon");
+    if (s) return s;
+    if (!d_vol || !d_proj || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_siddon: NULL pointer");
+    const Level &L = p->lv[level];
+    if (ws_bytes < (size_t)L.nvox() * sizeof(float))
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_siddon: workspace %zu < %zu bytes", ws_bytes,
+                              (size_t)L.nvox() * sizeof(float));
+    hipStream_t st = (hipStream_t)stream;
+    s = cbct_launch_to_columns(L, d_vol, (float *)d_ws, st);
+    if (s) return s;
+    return cbct_launch_forward_siddon(L, (const float *)d_ws, d_proj, st);
+}
+
+extern "C" cbct_status cbct_adjoint_siddon(const cbct_plan *p, int level, const float *d_proj, float *d_vol,
+                                           cbct_stream_t stream) {
+    cbct_status s = check_level(p, level, "adjoint_siddon");
+    if (s) return s;
+    if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: NULL pointer");
+    return cbct_launch_adjoint_siddon(p->lv[level], d_proj, d_vol, (hipStream_t)stream);
 }
 
 extern "C" cbct_status cbct_backproject_eq6(const cbct_plan *p, int level, const float *d_proj, float *d_vol,

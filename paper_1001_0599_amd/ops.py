@@ -133,6 +133,29 @@ class Plan:
         check(lib().cbct_backproject_eq6(self._h, level, y.data_ptr(), out.data_ptr(), _stream_handle(self.device)))
         return out
 
+    def forward_siddon(self, f: torch.Tensor, level: int = 0, out: torch.Tensor = None,
+                       workspace: torch.Tensor = None):
+        """Siddon's exact-path projection (cbct_forward_siddon)."""
+        _require(f, self.vol_shape(level), "f", self.device)
+        if out is None:
+            out = torch.empty(self.proj_shape(level), dtype=torch.float32, device=self.device)
+        _require(out, self.proj_shape(level), "out", self.device)
+        nb = self.forward_workspace_bytes(level)
+        if workspace is None or workspace.numel() * workspace.element_size() < nb:
+            workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check(lib().cbct_forward_siddon(self._h, level, f.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                        workspace.numel() * workspace.element_size(), _stream_handle(self.device)))
+        return out
+
+    def adjoint_siddon(self, y: torch.Tensor, level: int = 0, out: torch.Tensor = None):
+        """Transpose of the Siddon projection (cbct_adjoint_siddon)."""
+        _require(y, self.proj_shape(level), "y", self.device)
+        if out is None:
+            out = torch.empty(self.vol_shape(level), dtype=torch.float32, device=self.device)
+        _require(out, self.vol_shape(level), "out", self.device)
+        check(lib().cbct_adjoint_siddon(self._h, level, y.data_ptr(), out.data_ptr(), _stream_handle(self.device)))
+        return out
+
     # ---- solver ----------------------------------------------------------------------------
     @staticmethod
     def solve_params(lam=0.05, iters=(20,), levels=None, step=0.0, replay=None, **kw):

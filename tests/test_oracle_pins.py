@@ -172,6 +172,19 @@ def pin_siddon_box_and_identity():
     return e1 < 1e-12 and e2 < 1e-12, (e1, e2)
 
 
+def pin_siddon_sampled():
+    """The sampled Siddon entry points (used at full size) equal the full ones (1e-12): P at
+    selected rays, and P^T at selected voxels by per-cube chords over the projected footprint."""
+    g = SMALL
+    x = S.random_volume(g, 17, "normal")
+    y = S.random_projections(g, 18, "normal")
+    rays = np.arange(0, g.n_views * g.nv * g.nu, 7)
+    vox = np.arange(0, g.n_vox, 5)
+    e1 = _rel(O.forward_siddon_rays(g, x, rays), O.forward_siddon(g, x).ravel()[rays])
+    e2 = _rel(O.adjoint_siddon_voxels(g, y, vox), O.adjoint_siddon(g, y).ravel()[vox])
+    return max(e1, e2) < 1e-12, (e1, e2)
+
+
 def pin_siddon_chords():
     """Siddon P of a voxelised ball against its exact chords: rel-L2 <= 8 % at 2 mm and at least
     1.6x smaller on the 2x finer grid (first order: the ray integral of a piecewise-constant
@@ -416,7 +429,7 @@ def pin_constants():
 PINS = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_chords, pin_mass, pin_box,
         pin_centroid, pin_continuum_adjoint, pin_eq6_affine, pin_eq6_near_adjoint, pin_tv_gradient, pin_tv_closed_forms, pin_transfers,
         pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants, pin_convergence_rule,
-        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_chords]
+        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_sampled, pin_siddon_chords]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
