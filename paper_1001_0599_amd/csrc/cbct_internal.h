@@ -81,6 +81,7 @@ struct Level {
     // forward projector table geometry
     int fwd_pad;   // zero cells on either side of the z range in the ray-sample tables
     int fwd_kc;    // samples per table chunk
+    int fwd_kr;    // samples per chunk of the run-summing projector (0: its tables do not fit)
     int fwd_tw;    // table rows (z cells incl. padding)
     // adjoint
     AdjArgs adj;
@@ -115,6 +116,8 @@ cbct_status cbct_hip_error(hipError_t e, const char *what);
     } while (0)
 
 // kernel launchers (each checks its launch)
+// chunk of the run-summing projector for nz cells (0: its LDS tables do not fit)
+int cbct_forward_run_chunk(int nz);
 cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_t, hipStream_t s);
 // y_sub == NULL: out = P f.  Otherwise residual mode: out = w * (P f - y_sub) (the ray weight
 // applied, ready for the pre-weighted adjoint; plain P f - y_sub when weight_residual is false)

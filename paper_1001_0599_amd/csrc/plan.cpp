@@ -136,8 +136,8 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
             c.idfx = std::fabs(dfx) > 1e-12 ? (float)(1.0 / dfx) : 0.0f;
             c.idfy = std::fabs(dfy) > 1e-12 ? (float)(1.0 / dfy) : 0.0f;
             if (khi >= klo) {
-                // up to one chunk (<= 32 samples) is appended below to fill whole chunks
-                double gmax = (tau_c + (khi + 32) * L.dtau) * L.pv / (r * L.hz);
+                // up to one chunk (<= 64 samples) is appended below to fill whole chunks
+                double gmax = (tau_c + (khi + 64) * L.dtau) * L.pv / (r * L.hz);
                 smax = std::max(smax, gmax * 0.5 * (L.nv - 1));
             }
         }
@@ -148,7 +148,9 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     L.fwd_pad = std::max(0, (int)std::ceil(smax - beta)) + 1;
     L.fwd_tw = L.nz + 2 * L.fwd_pad + 3;
     L.fwd_kc = ((size_t)L.fwd_tw * 65 * 4 <= 56 * 1024) ? 32 : 16;
-    if ((size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4 > 60 * 1024)
+    // the run-summing projector (no z padding needed; 32-bit byte offsets into the volume)
+    L.fwd_kr = L.nvox() * 4 < (1L << 31) ? cbct_forward_run_chunk(L.nz) : 0;
+    if (L.fwd_kr == 0 && (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4 > 60 * 1024)
         return cbct_set_error(CBCT_ERR_INVALID_ARG,
                               "level %d: cone too wide for the projector tables (%d z cells)", l, L.fwd_tw);
     // adjoint profile workspace: the samples of each column inside the grid's support
@@ -170,16 +172,17 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
     A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
     A.sad = (float)L.sad; A.sdd = (float)L.sdd;
-    // whole chunks for the projector: extend every sample range to a multiple of the chunk (the
-    // extra samples lie beyond the grid, where all interpolation weights vanish)
+    // whole chunks for the projector: extend every sample range to a multiple of both chunk sizes
+    // (powers of two; the extra samples lie beyond the grid, where all interpolation weights vanish)
+    const int kpad = std::max(L.fwd_kc, L.fwd_kr);
     for (auto &c : cols)
-        if (c.khi >= c.klo) c.khi = c.klo + ((c.khi - c.klo + L.fwd_kc) / L.fwd_kc) * L.fwd_kc - 1;
+        if (c.khi >= c.klo) c.khi = c.klo + ((c.khi - c.klo + kpad) / kpad) * kpad - 1;
 
     if (std::getenv("CBCT_PLAN_REPORT"))
         std::fprintf(stderr,
-                     "[cbct plan] level %d: %dx%dx%d voxels, %d views %dx%d; fwd pad %d kc %d lds %zu; "
+                     "[cbct plan] level %d: %dx%dx%d voxels, %d views %dx%d; fwd pad %d kc %d kr %d lds %zu; "
                      "adjoint profiles %.1f MB\n",
-                     l, L.nx, L.ny, L.nz, L.nviews, L.nu, L.nv, L.fwd_pad, L.fwd_kc,
+                     l, L.nx, L.ny, L.nz, L.nviews, L.nu, L.nv, L.fwd_pad, L.fwd_kc, L.fwd_kr,
                      (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4, 4e-6 * (double)L.z_floats);
     CBCT_HIP(hipMalloc((void **)&L.d_cols, sizeof(ColParams) * cols.size()));
     CBCT_HIP(hipMalloc((void **)&L.d_views, sizeof(ViewParams) * views.size()));

@@ -209,6 +209,248 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// one float of the volume through a raw buffer resource (byte offset)
+__device__ __forceinline__ float ldv(__amdgpu_buffer_rsrc_t r, int off, int, int) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Forward projection by runs.  Within a chunk of KC samples a ray's z index s_k = s_a + k delta
+// (k local) stays in one z cell for long stretches (|delta| is a few hundredths of a cell per
+// sample), and on such a run the linear interpolation sums in closed form:
+//   sum_k [(1 - f_k) col_k[e] + f_k col_k[e+1]],  f_k = (s_a - e) + k delta,
+//   = dA_e + (s_a - e)(dA_{e+1} - dA_e) + delta (dK_{e+1} - dK_e),
+// with A_e(k) = sum_{k' < k} col_k'[e] and K_e(k) = sum_{k' < k} k' col_k'[e] prefix sums over the
+// chunk's samples.  So a ray costs O(runs) = O(chunks + z cells crossed) instead of O(samples).
+// Rows j and nv-1-j are mirror images (s' = nz + 1 - s, cell nz - e, fraction 1 - f): they leave
+// their cells at the same samples, so one thread sums both from one split computation.
+//
+// Per chunk: the first KC threads compute the samples' xy corner weights; wave w builds the prefix
+// sums of a contiguous slice of the chunk's samples for all z cells (lane = cell, the bilinear
+// column values from four z-contiguous voxel columns), the slices are joined by adding the earlier
+// slices' totals, and every thread then sums its pair of rays run by run.  The table is cell-major,
+// [e][k] with k = 0 .. KC: column e holds voxel e - 1; cells 0 and nz + 1 stay zero, so rays
+// leaving the slab read zeros.
+template <int KC>
+__host__ __device__ constexpr size_t runs_lds_bytes(int nz, int nwaves) {
+    return ((size_t)(nz + 2) * (KC + 1) * 8 + 15) / 16 * 16 + (size_t)KC * 32 + (size_t)nwaves * nz * 8;
+}
+
+template <int KC, int NPT>
+__global__ void __launch_bounds__(256)
+    k_forward_runs(const float *__restrict__ vol_t, const ColParams *__restrict__ cols, int nx, int ny, int nz, int nu,
+                   int nv, float pv, const float *__restrict__ ysub, int wres, float *__restrict__ out,
+                   double *__restrict__ partials) {
+    extern __shared__ float4 lds4[];
+    constexpr int S = KC + 1;  // entries per cell: (A, K) before local sample k = 0 .. KC
+    const int tw = nz + 2;
+    float2 *tab = reinterpret_cast<float2 *>(lds4);
+    float4 *kw = lds4 + ((size_t)tw * S * 8 + 15) / 16;
+    int4 *ko = reinterpret_cast<int4 *>(kw + KC);
+    float2 *tot = reinterpret_cast<float2 *>(ko + KC);  // [wave][nz]: slice totals
+    __shared__ double wsum[4];
+
+    const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int i = w % nu, view = w / nu;
+    const ColParams cp = cols[(long)view * nu + i];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+
+    // k = 0 and the two zero cells are never written again
+    for (int e = tid; e < tw; e += nthr) tab[e * S] = make_float2(0.0f, 0.0f);
+    for (int k = 1 + tid; k <= KC; k += nthr) {
+        tab[k] = make_float2(0.0f, 0.0f);
+        tab[(tw - 1) * S + k] = make_float2(0.0f, 0.0f);
+    }
+
+    // pair p: rays j = tid + p * nthr (q <= 0) and its mirror nv - 1 - j.  Ray j's z index (table
+    // units, voxel c at s = c + 1) is s_k = s0 + k delta; a run in cell e ends at the first sample
+    // past the boundary ahead, e + bo: k = ceil((e + bo - s_a) / delta) (a sample exactly on the
+    // boundary may go to either cell: the interpolant is continuous there).
+    const int npairs = (nv + 1) >> 1;
+    float s0[NPT], dl[NPT], idl[NPT], bo[NPT], acc[NPT], accm[NPT];
+#pragma unroll
+    for (int p = 0; p < NPT; p++) {
+        const int j = tid + p * nthr;
+        const float q = (j < npairs) ? (float)j - 0.5f * (float)(nv - 1) : 0.0f;
+        s0[p] = fmaf(cp.g0, q, 0.5f * (float)(nz - 1) + 1.0f);
+        dl[p] = cp.dg * q;
+        idl[p] = dl[p] != 0.0f ? 1.0f / dl[p] : 1e30f;
+        bo[p] = dl[p] >= 0.0f ? 1.0f : 0.0f;
+        acc[p] = 0.0f;
+        accm[p] = 0.0f;
+    }
+    // voxel loads through a raw buffer: 32-bit byte offsets, one add each
+    const __amdgpu_buffer_rsrc_t vrs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(vol_t), 0, nx * ny * nz * 4, 0x00020000);
+    const int sc = ((KC + nw - 1) / nw + 7) & ~7;  // slices of whole groups of 8 samples
+    const int ka = min(wave * sc, KC), kb = min(ka + sc, KC);
+
+    for (int k0 = cp.klo; k0 <= cp.khi; k0 += KC) {
+        __syncthreads();  // the previous chunk's rays are done with the tables
+        if (tid < KC) {
+            const float kf = (float)(k0 + tid);
+            const float fx = fmaf(kf, cp.dfx, cp.fx0), fy = fmaf(kf, cp.dfy, cp.fy0);
+            const float flx = floorf(fx), fly = floorf(fy);
+            const float wx = fx - flx, wy = fy - fly;
+            const int a = (int)flx, b = (int)fly;
+            const bool xa = (a >= 0 && a < nx), xb = (a + 1 >= 0 && a + 1 < nx);
+            const bool ya = (b >= 0 && b < ny), yb = (b + 1 >= 0 && b + 1 < ny);
+            const int ac0 = min(max(a, 0), nx - 1), ac1 = min(max(a + 1, 0), nx - 1);
+            const int bc0 = min(max(b, 0), ny - 1), bc1 = min(max(b + 1, 0), ny - 1);
+            kw[tid] = make_float4((xa && ya) ? (1.0f - wx) * (1.0f - wy) : 0.0f, (xb && ya) ? wx * (1.0f - wy) : 0.0f,
+                                  (xa && yb) ? (1.0f - wx) * wy : 0.0f, (xb && yb) ? wx * wy : 0.0f);
+            ko[tid] = make_int4((bc0 * nx + ac0) * nz * 4, (bc0 * nx + ac1) * nz * 4, (bc1 * nx + ac0) * nz * 4,
+                                (bc1 * nx + ac1) * nz * 4);  // byte offsets
+        }
+        __syncthreads();
+        // prefix sums of this wave's slice of samples, lane = z cell; groups of RB samples read
+        // their weights first and keep all their voxel loads in flight together
+        constexpr int RB = 8;
+        for (int c = lane; c < nz; c += 64) {
+            float A = 0.0f, K = 0.0f;
+            float2 *row = tab + (c + 1) * S + 1;  // entry k + 1 holds the sums over samples < k + 1
+            const int c4 = c * 4;
+            for (int kk = ka; kk < kb; kk += RB) {
+                float4 wq[RB];
+                int4 o[RB];
+#pragma unroll
+                for (int u = 0; u < RB; u++) {
+                    wq[u] = kw[kk + u];
+                    o[u] = ko[kk + u];
+                }
+                float v[RB][4];
+#pragma unroll
+                for (int u = 0; u < RB; u++) {
+                    v[u][0] = ldv(vrs, o[u].x + c4, 0, 0);
+                    v[u][1] = ldv(vrs, o[u].y + c4, 0, 0);
+                    v[u][2] = ldv(vrs, o[u].z + c4, 0, 0);
+                    v[u][3] = ldv(vrs, o[u].w + c4, 0, 0);
+                }
+                const float kf = (float)kk;
+#pragma unroll
+                for (int u = 0; u < RB; u++) {
+                    const float col =
+                        fmaf(wq[u].w, v[u][3], fmaf(wq[u].z, v[u][2], fmaf(wq[u].y, v[u][1], wq[u].x * v[u][0])));
+                    A += col;
+                    K = fmaf(kf + (float)u, col, K);
+                    row[kk + u] = make_float2(A, K);
+                }
+            }
+            tot[wave * nz + c] = make_float2(A, K);
+        }
+        __syncthreads();
+        if (wave > 0) {
+            for (int c = lane; c < nz; c += 64) {
+                float2 off = tot[c];
+                for (int w2 = 1; w2 < wave; w2++) {
+                    const float2 t = tot[w2 * nz + c];
+                    off.x += t.x;
+                    off.y += t.y;
+                }
+                float2 *row = tab + (c + 1) * S + 1;
+                for (int kk = ka; kk < kb; kk += RB) {
+                    float2 t[RB];
+#pragma unroll
+                    for (int u = 0; u < RB; u++) t[u] = row[kk + u];
+#pragma unroll
+                    for (int u = 0; u < RB; u++) row[kk + u] = make_float2(t[u].x + off.x, t[u].y + off.y);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < NPT; p++) {
+            const float sa = fmaf((float)k0, dl[p], s0[p]);
+            const float se = fmaf((float)(KC - 1), dl[p], sa);
+            // the mirror ray's index is nz + 1 - s: both read zeros only when ray j does
+            if (fmaxf(sa, se) < 0.0f || fminf(sa, se) >= (float)(tw - 1)) continue;
+            const int sg = dl[p] >= 0.0f ? 1 : -1;
+            float ef = floorf(sa);
+            int e = (int)ef, kp = 0;
+            float r = 0.0f, rm = 0.0f;
+            for (;;) {
+                // the runs in cell e (ray j) and cell nz - e (mirror): local samples [kp, kn)
+                const int kn = max((int)fminf(ceilf((ef + bo[p] - sa) * idl[p]), (float)KC), kp);
+                const int ec = min(max(e, 0), tw - 2), em = min(max(nz - e, 0), tw - 2);
+                const float2 *t = tab + ec * S, *tm = tab + em * S;
+                const float2 a1 = t[kn], b1 = t[kn + S], a0 = t[kp], b0 = t[kp + S];
+                const float2 c1 = tm[kn], d1 = tm[kn + S], c0 = tm[kp], d0 = tm[kp + S];
+                const float fe = sa - ef;
+                const float dA0 = a1.x - a0.x, dA1 = b1.x - b0.x, dK0 = a1.y - a0.y, dK1 = b1.y - b0.y;
+                const float run = fmaf(dl[p], dK1 - dK0, fmaf(fe, dA1 - dA0, dA0));
+                // mirror: fraction 1 - fe, step -delta
+                const float mA0 = c1.x - c0.x, mA1 = d1.x - d0.x, mK0 = c1.y - c0.y, mK1 = d1.y - d0.y;
+                const float runm = fmaf(-dl[p], mK1 - mK0, fmaf(1.0f - fe, mA1 - mA0, mA0));
+                r += (e == ec) ? run : 0.0f;
+                rm += (nz - e == em) ? runm : 0.0f;
+                if (kn >= KC) break;
+                kp = kn;
+                e += sg;
+                ef += (float)sg;
+            }
+            acc[p] += r;
+            accm[p] += rm;
+        }
+    }
+
+    double part = 0.0;
+#pragma unroll
+    for (int p = 0; p < NPT; p++) {
+        const int j = tid + p * nthr;
+        if (j < npairs) {
+            const int jm = nv - 1 - j;
+            const float v = ((float)j - 0.5f * (float)(nv - 1)) * pv;
+            const float wr = cp.wsc * sqrtf(fmaf(v, v, cp.r2));  // the mirror has the same weight
+            const long o1 = ((long)view * nv + j) * nu + i, o2 = ((long)view * nv + jm) * nu + i;
+            float r1 = wr * acc[p], r2 = wr * accm[p];
+            if (ysub) {
+                r1 -= ysub[o1];
+                r2 -= ysub[o2];
+                part += (double)r1 * (double)r1;
+                if (jm != j) part += (double)r2 * (double)r2;
+                if (wres) {
+                    r1 *= wr;
+                    r2 *= wr;
+                }
+            }
+            out[o1] = r1;
+            if (jm != j) out[o2] = r2;
+        }
+    }
+    if (partials) {
+        part = wave_sum(part);
+        if (lane == 0) wsum[wave] = part;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w2 = 0; w2 < nw; w2++) s += wsum[w2];
+            partials[(long)view * nu + i] = s;
+        }
+    }
+}
+
+template <int KC, int NPT>
+cbct_status launch_fwd_runs(const Level &L, const float *vol_t, const float *ysub, int wres, float *out,
+                            double *partials, hipStream_t s, int block) {
+    const size_t lds = runs_lds_bytes<KC>(L.nz, block / 64);
+    dim3 grid(L.nu, L.nviews);
+    hipLaunchKernelGGL((k_forward_runs<KC, NPT>), grid, dim3(block), lds, s, vol_t, L.d_cols, L.nx, L.ny, L.nz, L.nu,
+                       L.nv, (float)L.pv, ysub, wres, out, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cbct_hip_error(e, "k_forward_runs launch");
+    return CBCT_OK;
+}
+
+template <int KC>
+cbct_status dispatch_fwd_runs(const Level &L, const float *vol_t, const float *ysub, int wres, float *out,
+                              double *partials, hipStream_t s, int npt, int block) {
+    if (npt == 1) return launch_fwd_runs<KC, 1>(L, vol_t, ysub, wres, out, partials, s, block);
+    if (npt == 2) return launch_fwd_runs<KC, 2>(L, vol_t, ysub, wres, out, partials, s, block);
+    if (npt == 4) return launch_fwd_runs<KC, 4>(L, vol_t, ysub, wres, out, partials, s, block);
+    if (npt == 8) return launch_fwd_runs<KC, 8>(L, vol_t, ysub, wres, out, partials, s, block);
+    return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: %d detector rows is more than supported", L.nv);
+}
+
 template <int KC, int NPT, bool VEC>
 cbct_status launch_fwd(const Level &L, const float *vol_t, const float *ysub, int wres, float *out, double *partials,
                        hipStream_t s, int block) {
@@ -232,9 +474,30 @@ cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_
     return CBCT_OK;
 }
 
+int cbct_forward_run_chunk(int nz) {
+    constexpr size_t budget = 48 * 1024;
+    if (runs_lds_bytes<64>(nz, 4) <= budget) return 64;
+    if (runs_lds_bytes<32>(nz, 4) <= budget) return 32;
+    if (runs_lds_bytes<16>(nz, 4) <= budget) return 16;
+    if (runs_lds_bytes<8>(nz, 4) <= budget) return 8;
+    return 0;
+}
+
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *ysub, float *out, double *partials,
                                 hipStream_t s, bool weight_residual) {
     const int wres = weight_residual ? 1 : 0;
+    if (L.fwd_kr > 0) {
+        // rays per thread and a work-group size that splits the rows evenly
+        const int npairs = (L.nv + 1) / 2;
+        int npt = 1;
+        while ((npairs + npt - 1) / npt > 256) npt *= 2;
+        const int block = (((npairs + npt - 1) / npt + 63) / 64) * 64;
+        if (L.fwd_kr == 64) return dispatch_fwd_runs<64>(L, vol_t, ysub, wres, out, partials, s, npt, block);
+        if (L.fwd_kr == 32) return dispatch_fwd_runs<32>(L, vol_t, ysub, wres, out, partials, s, npt, block);
+        if (L.fwd_kr == 16) return dispatch_fwd_runs<16>(L, vol_t, ysub, wres, out, partials, s, npt, block);
+        if (L.fwd_kr == 8) return dispatch_fwd_runs<8>(L, vol_t, ysub, wres, out, partials, s, npt, block);
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: %d detector rows is more than supported", L.nv);
+    }
     const int npairs = (L.nv + 1) / 2;
     int block = ((npairs + 63) / 64) * 64;
     int npt = 1;
