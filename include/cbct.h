@@ -117,12 +117,19 @@ cbct_status cbct_backproject_eq6(const cbct_plan *plan, int level, const float *
 cbct_status cbct_forward_siddon(const cbct_plan *plan, int level, const float *d_vol, float *d_proj, void *d_ws,
                                 size_t ws_bytes, cbct_stream_t stream);
 
+/* Workspace (device bytes) of cbct_adjoint_siddon at `level`: a z profile (nz floats) for every
+ * piece of every detector column's transverse line (n_views x nu x (nx + ny + 3) x nz floats) plus
+ * 16 bytes per column. */
+cbct_status cbct_adjoint_siddon_workspace_size(const cbct_plan *plan, int level, size_t *bytes);
+
 /* Transpose of cbct_forward_siddon: d_vol = P_s^T d_proj (the matched backprojector; Section
  * II.C.2 explains why it is voxel-driven): each voxel gathers length x value over the rays that
- * cross its cube; every voxel of d_vol is written once, no atomics, no workspace.  Errors as
- * cbct_forward_siddon. */
-cbct_status cbct_adjoint_siddon(const cbct_plan *plan, int level, const float *d_proj, float *d_vol,
-                                cbct_stream_t stream);
+ * cross its cube.  d_proj [n_views][nv][nu], d_vol [nz][ny][nx] at `level`; d_ws: at least
+ * cbct_adjoint_siddon_workspace_size bytes, 256-byte aligned, overwritten.  Every voxel of d_vol is
+ * written once, no atomics.  INVALID_ARG on NULL pointers, a bad level or a small or misaligned
+ * workspace. */
+cbct_status cbct_adjoint_siddon(const cbct_plan *plan, int level, const float *d_proj, float *d_vol, void *d_ws,
+                                size_t ws_bytes, cbct_stream_t stream);
 
 /* Workspace (device bytes) of cbct_adjoint at `level`: the z profiles of every detector
  * column's samples (views x columns x samples in the grid's support x nz floats). */

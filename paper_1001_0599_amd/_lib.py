@@ -61,7 +61,8 @@ _SIG = [
     ("cbct_forward_columns", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_backproject_eq6", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_forward_siddon", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
-    ("cbct_adjoint_siddon", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
+    ("cbct_adjoint_siddon_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
+    ("cbct_adjoint_siddon", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
     ("cbct_adjoint_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
     ("cbct_adjoint", C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_size_t, _VP]),
     ("cbct_solve_params_default", None, [C.POINTER(SolveParams)]),

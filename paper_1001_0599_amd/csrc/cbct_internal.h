@@ -132,7 +132,9 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
                                 float *out, float *Zws, hipStream_t s, bool preweighted = false);
 // Siddon pair: out = P_s vol_t (vol_t in the column-major layout) and out = P_s^T proj.
 cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float *out, hipStream_t s);
-cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, hipStream_t s);
+// P_s^T through per-piece z profiles in ws (cbct_adjoint_siddon_ws_bytes), or the per-cell gather
+cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, void *ws, hipStream_t s);
+size_t cbct_adjoint_siddon_ws_bytes(const Level &L);
 
 // ---- solver pieces --------------------------------------------------------------------------
 constexpr int CBCT_RED_BLOCKS = 8192;  // work-groups of the fixed-size reduction grids

@@ -339,12 +339,26 @@ extern "C" cbct_status cbct_forward_siddon(const cbct_plan *p, int level, const 
     return cbct_launch_forward_siddon(L, (const float *)d_ws, d_proj, st);
 }
 
+extern "C" cbct_status cbct_adjoint_siddon_workspace_size(const cbct_plan *p, int level, size_t *bytes) {
+    cbct_status s = check_level(p, level, "adjoint_siddon_workspace_size");
+    if (s) return s;
+    if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon_workspace_size: NULL out");
+    *bytes = cbct_adjoint_siddon_ws_bytes(p->lv[level]);
+    return CBCT_OK;
+}
+
 extern "C" cbct_status cbct_adjoint_siddon(const cbct_plan *p, int level, const float *d_proj, float *d_vol,
-                                           cbct_stream_t stream) {
+                                           void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "adjoint_siddon");
     if (s) return s;
-    if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: NULL pointer");
-    return cbct_launch_adjoint_siddon(p->lv[level], d_proj, d_vol, (hipStream_t)stream);
+    if (!d_proj || !d_vol || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: NULL pointer");
+    const Level &L = p->lv[level];
+    const size_t need = cbct_adjoint_siddon_ws_bytes(L);
+    if (ws_bytes < need)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)d_ws & 255) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: workspace must be 256-byte aligned");
+    return cbct_launch_adjoint_siddon(L, d_proj, d_vol, d_ws, (hipStream_t)stream);
 }
 
 extern "C" cbct_status cbct_backproject_eq6(const cbct_plan *p, int level, const float *d_proj, float *d_vol,

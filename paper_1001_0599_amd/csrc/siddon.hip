@@ -257,6 +257,45 @@ struct SidLine {  // the crossings of one column's xy line, both axes
     }
 };
 
+// The pieces of the line of column c inside the grid (entry tin < exit tout): pst[0 .. K] the
+// piece starts (pst[K] = tout) and, when pof is given, pof[0 .. K-1] the element offset of each
+// piece's voxel column (-1 outside the grid).  Piece 0 is the entry cell ln.a0, ln.b0; one piece
+// follows every crossing, placed at its rank in the stable merge of the two axes' crossings (x
+// first on ties), so piece k lies in voxel column (a0 + sx dx, b0 + sy dy) with dx + dy = k.  All
+// threads of the work-group take part; the caller synchronises before reading.
+__device__ int sid_piece_list(const SidCol &c, const SidArgs &A, float tin, float tout, int kmax, float *pst,
+                              int *pof, int tid, int nthr, SidLine &ln) {
+    ln.cx = c.cx; ln.cy = c.cy; ln.iex = c.iex; ln.iey = c.iey;
+    ln.nx = A.nx; ln.ny = A.ny; ln.hx = A.hx; ln.hy = A.hy;
+    ln.a0 = min(max(sid_cell(fmaf(tin, c.ex, c.cx), A.nx, A.hx), 0), A.nx - 1);
+    ln.b0 = min(max(sid_cell(fmaf(tin, c.ey, c.cy), A.ny, A.hy), 0), A.ny - 1);
+    if (c.iex == 0.0f) ln.a0 = sid_cell(c.cx, A.nx, A.hx);
+    if (c.iey == 0.0f) ln.b0 = sid_cell(c.cy, A.ny, A.hy);
+    ln.sx = c.ex > 0.0f ? 1 : -1;
+    ln.sy = c.ey > 0.0f ? 1 : -1;
+    const int mxc = ln.count_x(tout, c.ex, true), myc = ln.count_y(tout, c.ey, true);
+    const int K = min(mxc + myc + 1, kmax);
+    auto put = [&](int p, float t, int a, int b) {
+        pst[p] = fminf(fmaxf(t, tin), tout);
+        if (pof) pof[p] = (a >= 0 && a < A.nx && b >= 0 && b < A.ny) ? (b * A.nx + a) * A.nz : -1;
+    };
+    if (tid == 0) {
+        put(0, tin, ln.a0, ln.b0);
+        pst[K] = tout;
+    }
+    for (int m = tid; m < mxc; m += nthr) {
+        const float t = ln.tx(m);
+        const int p = m + ln.count_y(t, c.ey, true);  // y crossings strictly before: x first on ties
+        if (p + 1 < K) put(p + 1, t, ln.a0 + ln.sx * (m + 1), ln.b0 + ln.sy * (p - m));
+    }
+    for (int n = tid; n < myc; n += nthr) {
+        const float t = ln.ty(n);
+        const int p = n + ln.count_x(t, c.ex, false);
+        if (p + 1 < K) put(p + 1, t, ln.a0 + ln.sx * (p - n), ln.b0 + ln.sy * (n + 1));
+    }
+    return K;
+}
+
 template <int KP, int NPT>
 __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__restrict__ vol_t,
                                                              const SidCol *__restrict__ cols, SidArgs A, int kmax,
@@ -285,36 +324,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
 
     if (tin < tout) {  // uniform over the work-group
         SidLine ln;
-        ln.cx = c.cx; ln.cy = c.cy; ln.iex = c.iex; ln.iey = c.iey;
-        ln.nx = A.nx; ln.ny = A.ny; ln.hx = A.hx; ln.hy = A.hy;
-        ln.a0 = min(max(sid_cell(fmaf(tin, c.ex, c.cx), A.nx, A.hx), 0), A.nx - 1);
-        ln.b0 = min(max(sid_cell(fmaf(tin, c.ey, c.cy), A.ny, A.hy), 0), A.ny - 1);
-        if (c.iex == 0.0f) ln.a0 = sid_cell(c.cx, A.nx, A.hx);
-        if (c.iey == 0.0f) ln.b0 = sid_cell(c.cy, A.ny, A.hy);
-        ln.sx = c.ex > 0.0f ? 1 : -1;
-        ln.sy = c.ey > 0.0f ? 1 : -1;
-        const int mxc = ln.count_x(tout, c.ex, true), myc = ln.count_y(tout, c.ey, true);
-        const int K = min(mxc + myc + 1, kmax);
-        // the piece list: piece 0 at the entry, then one piece after every crossing
-        auto put = [&](int p, float t, int a, int b) {
-            pst[p] = fminf(fmaxf(t, tin), tout);
-            const bool in = a >= 0 && a < A.nx && b >= 0 && b < A.ny;
-            pof[p] = in ? (b * A.nx + a) * nz : -1;
-        };
-        if (tid == 0) {
-            put(0, tin, ln.a0, ln.b0);
-            pst[K] = tout;
-        }
-        for (int m = tid; m < mxc; m += nthr) {
-            const float t = ln.tx(m);
-            const int p = m + ln.count_y(t, c.ey, true);  // y crossings strictly before: x first on ties
-            if (p + 1 < K) put(p + 1, t, ln.a0 + ln.sx * (m + 1), ln.b0 + ln.sy * (p - m));
-        }
-        for (int n = tid; n < myc; n += nthr) {
-            const float t = ln.ty(n);
-            const int p = n + ln.count_x(t, c.ex, false);
-            if (p + 1 < K) put(p + 1, t, ln.a0 + ln.sx * (p - n), ln.b0 + ln.sy * (n + 1));
-        }
+        const int K = sid_piece_list(c, A, tin, tout, kmax, pst, pof, tid, nthr, ln);
 
         // rays: pair p = row j (v <= 0) and its mirror nv - 1 - j; z state of row j
         float ikz[NPT], t0r[NPT];
@@ -431,6 +441,194 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
     }
 }
 
+// Siddon transpose, pass 1: for every piece k of column i's line and z cell c,
+//   Z_k(c) = sum_j w_j y_j |piece k  n  {tau : ray j in cell c}|,
+// as Z_k(c) = W_{c+1}(k) - W_c(k), W_p(k) the integral over piece k of U_p(tau), the sum of w y over
+// the rows whose ray lies below z plane p at tau.  Those rows are a prefix j < J_p(tau) of the rows
+// (sorted by detector height v: ray j is below the plane where v_j < z_p lxy / (tau + t0)), and J
+// changes inside a piece only for the few rows whose ray crosses the plane there:
+//   W_p = len A(J_lo) + sum over J_lo <= j < J_hi of w_j y_j (time of ray j below the plane),
+// A the prefix sum of w y over the rows (accumulated in FP64), the crossing time from the same
+// expression as the forward kernel's.  Z is formed as len (A(J_lo, p+1) - A(J_lo, p)) + (difference
+// of the crossing terms), so FP32 suffices.  One work-group per (view, column); lane = piece, 16
+// cells at a time staged in LDS and stored as whole 64-byte runs; profiles go to
+// Z[(view nu + i) kmax + k][c], and rec[view nu + i] = (entry cell a0, b0, piece count K).
+constexpr int SPC = 16;  // cells per staged block of the profiles
+
+__global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ proj, const SidCol *__restrict__ cols,
+                                                      SidArgs A, int kmax, float *__restrict__ Z,
+                                                      int4 *__restrict__ rec) {
+    extern __shared__ float ldsf[];
+    const int nv = A.nv, nz = A.nz;
+    float *Af = ldsf;                // [nv + 1]: prefix of w y
+    float *wyf = Af + nv + 1;        // [nv]: w y
+    float *ivf = wyf + nv;           // [nv]: lxy / v (0 for v = 0)
+    float *pst = ivf + nv;           // [kmax + 1]
+    float *stg = pst + kmax + 1;     // [4][64][SPC + 1]
+    const int vc = cbct_xcd_remap(blockIdx.x, gridDim.x);
+    const int view = vc / A.nu, i = vc - view * A.nu;
+    const SidCol c = cols[vc];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+    float tin = -c.t0, tout = c.lxy - c.t0;
+    sid_slab(c.cx, c.iex, 0, A.nx, A.nx, A.hx, tin, tout);
+    sid_slab(c.cy, c.iey, 0, A.ny, A.ny, A.hy, tin, tout);
+    if (!(tin < tout)) {  // uniform: the line misses the grid
+        if (tid == 0) rec[vc] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    for (int j = tid; j < nv; j += nthr) {
+        const float v = sid_row_v(j, A), kz = v * c.ilxy;
+        wyf[j] = sqrtf(fmaf(kz, kz, 1.0f)) * proj[((long)view * nv + j) * A.nu + i];
+        ivf[j] = v != 0.0f ? c.lxy * (1.0f / v) : 0.0f;
+    }
+    __syncthreads();
+    if (tid < 64) {  // prefix over the rows in FP64, lane l taking rows [l R, (l + 1) R)
+        const int R = (nv + 63) / 64;
+        double s = 0.0;
+        for (int r = 0; r < R; r++) {
+            const int j = lane * R + r;
+            if (j < nv) s += (double)wyf[j];
+        }
+        double incl = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const double t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        double run = incl - s;
+        for (int r = 0; r < R; r++) {
+            const int j = lane * R + r;
+            if (j < nv) {
+                Af[j] = (float)run;
+                run += (double)wyf[j];
+            }
+        }
+        if (lane == 63) Af[nv] = (float)incl;
+    }
+    SidLine ln;
+    const int K = sid_piece_list(c, A, tin, tout, kmax, pst, nullptr, tid, nthr, ln);
+    if (tid == 0) rec[vc] = make_int4(ln.a0, ln.b0, K, 0);
+    __syncthreads();
+    float *Zl = Z + (long)vc * kmax * nz;
+    float *st = stg + wave * 64 * (SPC + 1);
+    const float cj = 0.5f * (float)(nv - 1), ipv = 1.0f / A.pv;
+    const bool vec = (nz & 3) == 0;
+    for (int kb = wave * 64; kb < K; kb += nw * 64) {  // uniform per wave
+        const int k = kb + lane;
+        const bool live = k < K;
+        const float ta = live ? pst[k] : 0.0f, tb = live ? pst[k + 1] : 0.0f, len = tb - ta;
+        const float isa = 1.0f / ((ta + c.t0) * c.ilxy), isb = 1.0f / ((tb + c.t0) * c.ilxy);
+        // (A(J_lo), crossing term) at plane p
+        auto plane_terms = [&](int p, float &alo, float &part) {
+            const float zp = sid_plane(p, nz, A.hz);
+            const float xa = zp * isa, xb = zp * isb;
+            // rows with v_j < x: j < x / pv + (nv - 1) / 2
+            const int jl = (int)fminf(fmaxf(ceilf(fmaf(fminf(xa, xb), ipv, cj)), 0.0f), (float)nv);
+            const int jh = (int)fminf(fmaxf(ceilf(fmaf(fmaxf(xa, xb), ipv, cj)), 0.0f), (float)nv);
+            alo = Af[jl];
+            part = 0.0f;
+            for (int j = jl; j < jh; j++) {
+                const float th = fmaf(zp, ivf[j], -c.t0);  // the forward kernel's crossing of plane p
+                part = fmaf(wyf[j], fminf(fmaxf(zp > 0.0f ? th - ta : tb - th, 0.0f), len), part);
+            }
+        };
+        float pa, pp;
+        plane_terms(0, pa, pp);
+        for (int c0 = 0; c0 < nz; c0 += SPC) {
+#pragma unroll 4
+            for (int u = 0; u < SPC; u++) {
+                if (c0 + u < nz) {
+                    float na, np;
+                    plane_terms(c0 + u + 1, na, np);
+                    st[lane * (SPC + 1) + u] = fmaf(len, na - pa, np - pp);
+                    pa = na;
+                    pp = np;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // the wave's 64 pieces x SPC cells: lane pairs (piece, group of 4 cells)
+            for (int r = lane; r < 64 * (SPC / 4); r += 64) {
+                const int pc = r / (SPC / 4), g4 = (r - pc * (SPC / 4)) * 4;
+                const int kk = kb + pc, cc = c0 + g4;
+                if (kk < K && cc < nz) {
+                    const float *sv = st + pc * (SPC + 1) + g4;
+                    float *dst = Zl + (long)kk * nz + cc;
+                    if (vec) {
+                        *reinterpret_cast<float4 *>(dst) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+                    } else {
+                        for (int u = 0; u < 4 && cc + u < nz; u++) dst[u] = sv[u];
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Siddon transpose, pass 2: a thread owns 4 z cells of one voxel column (a, b); per view and per
+// detector column whose line crosses the column's square, the crossing is piece k = |a - a0| +
+// |b - b0| of that line, whose profile it adds.  Work-group: 4 x 4 voxel columns x 16 groups of 4
+// cells (64 cells; blockIdx.y picks the z block).  Every voxel is written once; no atomics.
+__global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restrict__ Z, const int4 *__restrict__ rec,
+                                                           const SidCol *__restrict__ cols,
+                                                           const ViewParams *__restrict__ views, SidArgs A, int kmax,
+                                                           float *__restrict__ out) {
+    const int ntx = (A.nx + 3) / 4;
+    const int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
+    const int g = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int a = (w % ntx) * 4 + (q & 3), b = (w / ntx) * 4 + (q >> 2);
+    const int c0 = blockIdx.y * 64 + g * 4;
+    if (a >= A.nx || b >= A.ny || c0 >= A.nz) return;  // no barriers below
+    const int nz = A.nz;
+    const bool vec = (nz & 3) == 0;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float xa = sid_plane(a, A.nx, A.hx), xb = sid_plane(a + 1, A.nx, A.hx);
+    const float ya = sid_plane(b, A.ny, A.hy), yb = sid_plane(b + 1, A.ny, A.hy);
+    const float iu = 0.5f * (float)(A.nu - 1);
+    for (int view = 0; view < A.nviews; view++) {
+        const ViewParams vp = views[view];
+        float umin = SID_INF, umax = -SID_INF;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const float x = (r & 1) ? xb : xa, y = (r & 2) ? yb : ya;
+            const float u = A.sdd * (x * vp.sn - y * vp.cs) / (x * vp.cs + y * vp.sn + A.sad);
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+        }
+        const int i0 = max((int)floorf(umin / A.pu + iu), 0), i1 = min((int)ceilf(umax / A.pu + iu), A.nu - 1);
+        for (int i = i0; i <= i1; i++) {
+            const long vc = (long)view * A.nu + i;
+            const SidCol c = cols[vc];
+            float ta = -c.t0, tb = c.lxy - c.t0;
+            sid_slab(c.cx, c.iex, a, a + 1, A.nx, A.hx, ta, tb);
+            sid_slab(c.cy, c.iey, b, b + 1, A.ny, A.hy, ta, tb);
+            if (!(ta < tb)) continue;
+            const int4 r = rec[vc];
+            const int k = abs(a - r.x) + abs(b - r.y);
+            if (k >= r.z) continue;
+            const float *zl = Z + (vc * kmax + k) * nz + c0;
+            if (vec) {
+                const float4 z4 = *reinterpret_cast<const float4 *>(zl);
+                acc[0] += z4.x;
+                acc[1] += z4.y;
+                acc[2] += z4.z;
+                acc[3] += z4.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if (c0 + u < nz) acc[u] += zl[u];
+            }
+        }
+    }
+    const long plane = (long)A.nx * A.ny;
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        if (c0 + u < nz) out[(c0 + u) * plane + (long)b * A.nx + a] = acc[u];
+}
+
 SidArgs sid_args(const Level &L) {
     SidArgs A;
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
@@ -485,7 +683,30 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, hipStream_t s) {
+size_t cbct_adjoint_siddon_ws_bytes(const Level &L) {
+    const size_t lines = (size_t)L.nviews * L.nu;
+    const size_t kmax = (size_t)L.nx + L.ny + 3;
+    return ((lines * kmax * L.nz * 4 + 255) & ~(size_t)255) + lines * 16;
+}
+
+cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, void *ws, hipStream_t s) {
+    const int kmax = L.nx + L.ny + 3;
+    const size_t lds = (size_t)(3 * L.nv + 1) * 4 + (size_t)(kmax + 1) * 4 + (size_t)4 * 64 * (16 + 1) * 4;
+    if (lds <= 64 * 1024) {
+        const size_t lines = (size_t)L.nviews * L.nu;
+        float *Z = static_cast<float *>(ws);
+        int4 *rec = reinterpret_cast<int4 *>(static_cast<char *>(ws) + ((lines * kmax * L.nz * 4 + 255) & ~(size_t)255));
+        hipLaunchKernelGGL(k_sid_profiles, dim3((unsigned)lines), dim3(256), lds, s, proj, L.d_sid, sid_args(L), kmax, Z,
+                           rec);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return cbct_hip_error(e, "k_sid_profiles launch");
+        const dim3 grid((unsigned)(((L.nx + 3) / 4) * ((L.ny + 3) / 4)), (unsigned)((L.nz + 63) / 64));
+        hipLaunchKernelGGL(k_sid_gather_pieces, grid, dim3(256), 0, s, Z, rec, L.d_sid, L.d_views, sid_args(L), kmax,
+                           out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cbct_hip_error(e, "k_sid_gather_pieces launch");
+        return CBCT_OK;
+    }
     const long blocks = (long)((L.nx + 15) / 16) * ((L.ny + 15) / 16) * ((L.nz + SID_TZ - 1) / SID_TZ);
     if (blocks > 0x7fffffffL) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: grid too large");
     hipLaunchKernelGGL(k_siddon_gather, dim3((unsigned)blocks), dim3(256), 0, s, proj, L.d_sid, L.d_views, sid_args(L),

@@ -147,13 +147,23 @@ class Plan:
                                         workspace.numel() * workspace.element_size(), _stream_handle(self.device)))
         return out
 
-    def adjoint_siddon(self, y: torch.Tensor, level: int = 0, out: torch.Tensor = None):
+    def adjoint_siddon_workspace_bytes(self, level: int = 0) -> int:
+        n = C.c_size_t()
+        check(lib().cbct_adjoint_siddon_workspace_size(self._h, level, C.byref(n)))
+        return int(n.value)
+
+    def adjoint_siddon(self, y: torch.Tensor, level: int = 0, out: torch.Tensor = None,
+                       workspace: torch.Tensor = None):
         """Transpose of the Siddon projection (cbct_adjoint_siddon)."""
         _require(y, self.proj_shape(level), "y", self.device)
         if out is None:
             out = torch.empty(self.vol_shape(level), dtype=torch.float32, device=self.device)
         _require(out, self.vol_shape(level), "out", self.device)
-        check(lib().cbct_adjoint_siddon(self._h, level, y.data_ptr(), out.data_ptr(), _stream_handle(self.device)))
+        nb = self.adjoint_siddon_workspace_bytes(level)
+        if workspace is None or workspace.numel() * workspace.element_size() < nb:
+            workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check(lib().cbct_adjoint_siddon(self._h, level, y.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                        workspace.numel() * workspace.element_size(), _stream_handle(self.device)))
         return out
 
     # ---- solver ----------------------------------------------------------------------------

@@ -63,6 +63,6 @@ def test_calls_reject_null_plan():
     assert L.cbct_adjoint(None, 0, None, None, None, 0, None) == 1
     assert L.cbct_backproject_eq6(None, 0, None, None, None) == 1
     assert L.cbct_forward_siddon(None, 0, None, None, None, 0, None) == 1
-    assert L.cbct_adjoint_siddon(None, 0, None, None, None) == 1
+    assert L.cbct_adjoint_siddon(None, 0, None, None, None, 0, None) == 1
     n = C.c_size_t()
     assert L.cbct_forward_workspace_size(None, 0, C.byref(n)) == 1

@@ -103,4 +103,6 @@ def test_siddon_deterministic_and_validation():
     L = _lib.lib()
     assert L.cbct_forward_siddon(plan.handle, 0, x.data_ptr(), y.data_ptr(), x.data_ptr(), 16, None) == 1
     assert L.cbct_forward_siddon(plan.handle, 1, x.data_ptr(), y.data_ptr(), x.data_ptr(), 4 * x.numel(), None) == 1
-    assert L.cbct_adjoint_siddon(plan.handle, 0, y.data_ptr(), None, None) == 1
+    assert L.cbct_adjoint_siddon(plan.handle, 0, y.data_ptr(), None, x.data_ptr(), 1 << 30, None) == 1
+    ws = torch.empty(plan.adjoint_siddon_workspace_bytes(0), dtype=torch.uint8, device="cuda")
+    assert L.cbct_adjoint_siddon(plan.handle, 0, y.data_ptr(), x.data_ptr(), ws.data_ptr(), 64, None) == 1
