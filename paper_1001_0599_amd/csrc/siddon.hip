@@ -568,23 +568,27 @@ __global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ 
     }
 }
 
-// Siddon transpose, pass 2: a thread owns 4 z cells of one voxel column (a, b); per view and per
+// Siddon transpose, pass 2: a thread owns SGC z cells of one voxel column (a, b); per view and per
 // detector column whose line crosses the column's square, the crossing is piece k = |a - a0| +
-// |b - b0| of that line, whose profile it adds.  Work-group: 4 x 4 voxel columns x 16 groups of 4
-// cells (64 cells; blockIdx.y picks the z block).  Every voxel is written once; no atomics.
+// |b - b0| of that line, whose profile it adds.  Work-group: 8 x 8 voxel columns x 4 groups of SGC
+// cells (blockIdx.y picks the z block of 4 SGC cells).  Every voxel is written once; no atomics.
+constexpr int SGC = 16;
+
 __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restrict__ Z, const int4 *__restrict__ rec,
                                                            const SidCol *__restrict__ cols,
                                                            const ViewParams *__restrict__ views, SidArgs A, int kmax,
                                                            float *__restrict__ out) {
-    const int ntx = (A.nx + 3) / 4;
+    const int ntx = (A.nx + 7) / 8;
     const int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
-    const int g = threadIdx.x & 15, q = threadIdx.x >> 4;
-    const int a = (w % ntx) * 4 + (q & 3), b = (w / ntx) * 4 + (q >> 2);
-    const int c0 = blockIdx.y * 64 + g * 4;
+    const int g = threadIdx.x & 3, q = threadIdx.x >> 2;
+    const int a = (w % ntx) * 8 + (q & 7), b = (w / ntx) * 8 + (q >> 3);
+    const int c0 = (blockIdx.y * 4 + g) * SGC;
     if (a >= A.nx || b >= A.ny || c0 >= A.nz) return;  // no barriers below
     const int nz = A.nz;
     const bool vec = (nz & 3) == 0;
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[SGC];
+#pragma unroll
+    for (int u = 0; u < SGC; u++) acc[u] = 0.0f;
     const float xa = sid_plane(a, A.nx, A.hx), xb = sid_plane(a + 1, A.nx, A.hx);
     const float ya = sid_plane(b, A.ny, A.hy), yb = sid_plane(b + 1, A.ny, A.hy);
     const float iu = 0.5f * (float)(A.nu - 1);
@@ -610,22 +614,25 @@ __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restri
             const int k = abs(a - r.x) + abs(b - r.y);
             if (k >= r.z) continue;
             const float *zl = Z + (vc * kmax + k) * nz + c0;
-            if (vec) {
-                const float4 z4 = *reinterpret_cast<const float4 *>(zl);
-                acc[0] += z4.x;
-                acc[1] += z4.y;
-                acc[2] += z4.z;
-                acc[3] += z4.w;
+            if (vec && c0 + SGC <= nz) {
+#pragma unroll
+                for (int u = 0; u < SGC; u += 4) {
+                    const float4 z4 = *reinterpret_cast<const float4 *>(zl + u);
+                    acc[u] += z4.x;
+                    acc[u + 1] += z4.y;
+                    acc[u + 2] += z4.z;
+                    acc[u + 3] += z4.w;
+                }
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; u++)
+                for (int u = 0; u < SGC; u++)
                     if (c0 + u < nz) acc[u] += zl[u];
             }
         }
     }
     const long plane = (long)A.nx * A.ny;
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int u = 0; u < SGC; u++)
         if (c0 + u < nz) out[(c0 + u) * plane + (long)b * A.nx + a] = acc[u];
 }
 
@@ -700,7 +707,7 @@ cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float 
                            rec);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return cbct_hip_error(e, "k_sid_profiles launch");
-        const dim3 grid((unsigned)(((L.nx + 3) / 4) * ((L.ny + 3) / 4)), (unsigned)((L.nz + 63) / 64));
+        const dim3 grid((unsigned)(((L.nx + 7) / 8) * ((L.ny + 7) / 8)), (unsigned)((L.nz + 4 * SGC - 1) / (4 * SGC)));
         hipLaunchKernelGGL(k_sid_gather_pieces, grid, dim3(256), 0, s, Z, rec, L.d_sid, L.d_views, sid_args(L), kmax,
                            out);
         e = hipGetLastError();
