@@ -222,7 +222,12 @@ __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__
 
 // pieces per chunk for nz cells and a line of up to kmax pieces (0: the tables do not fit)
 inline size_t sid_runs_lds(int kp, int nz, int kmax, int nwaves) {
-    return (size_t)nz * (kp + 1) * 8 + (size_t)(2 * kmax + 2) * 4 + (size_t)nwaves * nz * 4;
+    return (size_t)nz * (kp + 1) * 8 + (size_t)(2 * kmax + 2) * 4 + (size_t)(kmax + kp) * 8 + (size_t)nwaves * nz * 4;
+}
+
+// one float of the volume through a raw buffer resource at a byte offset; offsets past the end read 0
+__device__ __forceinline__ float sid_ldv(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
 struct SidLine {  // the crossings of one column's xy line, both axes
@@ -306,7 +311,8 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
     float2 *tab = reinterpret_cast<float2 *>(lds4);
     float *pst = reinterpret_cast<float *>(tab + nz * S);  // piece starts, pst[K] = exit
     int *pof = reinterpret_cast<int *>(pst + kmax + 1);    // voxel-column element offset, -1 outside
-    float *tot = reinterpret_cast<float *>(pof + kmax + 1);  // [wave][nz]: slice totals
+    float2 *pk = reinterpret_cast<float2 *>(pof + kmax + 1);  // [kmax + KP]: (length, byte offset bits)
+    float *tot = reinterpret_cast<float *>(pk + kmax + KP);  // [wave][nz]: slice totals
 
     const int vc = cbct_xcd_remap(blockIdx.x, gridDim.x);  // view * nu + column
     const int view = vc / A.nu, i = vc - view * A.nu;
@@ -325,6 +331,17 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
     if (tin < tout) {  // uniform over the work-group
         SidLine ln;
         const int K = sid_piece_list(c, A, tin, tout, kmax, pst, pof, tid, nthr, ln);
+        __syncthreads();
+        // per piece: length and the byte offset of its voxel column; outside the grid, and past the
+        // last piece up to the chunk edge, an offset past the end of the volume (reads 0)
+        const int kr = (K + KP - 1) / KP * KP;
+        for (int k = tid; k < kr; k += nthr) {
+            const bool in = k < K && pof[k] >= 0;
+            pk[k] = make_float2(k < K ? pst[k + 1] - pst[k] : 0.0f, __int_as_float(in ? pof[k] * 4 : 0x7fffffff));
+        }
+        const __amdgpu_buffer_rsrc_t vrs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(vol_t), 0, A.nx * A.ny * nz * 4, 0x00020000);
+        const float ihx = 1.0f / A.hx, ihy = 1.0f / A.hy;
 
         // rays: pair p = row j (v <= 0) and its mirror nv - 1 - j; z state of row j
         float ikz[NPT], t0r[NPT];
@@ -342,30 +359,28 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
         }
         const int sc = ((KP + nw - 1) / nw + 7) & ~7;
         const int ka = min(wave * sc, KP), kb = min(ka + sc, KP);
-        const int olast = (A.nx * A.ny - 1) * nz;  // last voxel column's offset
         for (int k0 = 0; k0 < K; k0 += KP) {
             const int kn = min(KP, K - k0);
             __syncthreads();  // the piece list is complete / the previous chunk's rays are done
-            // Q of this wave's slice of pieces, lane = z cell; groups of 8 pieces keep their loads
-            // in flight together
-            const int kbe = min(kb, kn);
+            // Q of this wave's slice of pieces (whole groups of 8; pieces past the list have length
+            // 0 and read 0), lane = z cell; a group's loads are in flight together
+            constexpr int GB = 8;
             for (int cc = lane; cc < nz; cc += 64) {
                 float q = 0.0f;
                 float2 *row = tab + cc * S;
-                for (int k = ka; k < kbe; k += 8) {
-                    float f[8];
+                const int c4 = cc * 4;
+                for (int k = ka; k < kb; k += GB) {
+                    float2 pe[GB];
+                    float f[GB];
 #pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const int o = (k + u < kbe) ? pof[k0 + k + u] : -1;
-                        f[u] = (o >= 0 && o <= olast) ? vol_t[o + cc] : 0.0f;
+                    for (int u = 0; u < GB; u++) {
+                        pe[u] = pk[k0 + k + u];
+                        f[u] = sid_ldv(vrs, __float_as_int(pe[u].y) + c4);
                     }
 #pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        if (k + u < kbe) {
-                            const float len = pst[k0 + k + u + 1] - pst[k0 + k + u];
-                            row[k + u] = make_float2(q, f[u]);
-                            q = fmaf(f[u], len, q);
-                        }
+                    for (int u = 0; u < GB; u++) {
+                        row[k + u] = make_float2(q, f[u]);
+                        q = fmaf(f[u], pe[u].x, q);
                     }
                 }
                 tot[wave * nz + cc] = q;
@@ -375,7 +390,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
                 float off = 0.0f;
                 for (int w2 = 0; w2 < wave; w2++) off += tot[w2 * nz + cc];
                 if (wave > 0)
-                    for (int k = ka; k < kbe; k++) tab[cc * S + k].x += off;
+                    for (int k = ka; k < kb; k++) tab[cc * S + k].x += off;
                 if (wave == nw - 1) {  // the chunk's total for every cell
                     float all = off;
                     for (int w2 = wave; w2 < nw; w2++) all += tot[w2 * nz + cc];
@@ -399,10 +414,14 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
                     float dt = 0.0f;
                     if (cross) {
                         // the piece holding tz: one piece per x or y step from the entry
-                        const int a = c.iex != 0.0f ? min(max(sid_cell(fmaf(tz, c.ex, c.cx), A.nx, A.hx), 0), A.nx - 1)
-                                                    : ln.a0;
-                        const int b = c.iey != 0.0f ? min(max(sid_cell(fmaf(tz, c.ey, c.cy), A.ny, A.hy), 0), A.ny - 1)
-                                                    : ln.b0;
+                        // (a multiply for the cell: off by one only within rounding of a plane, where
+                        // the neighbouring piece's Q agrees)
+                        const int a = c.iex != 0.0f
+                                          ? min(max((int)floorf(fmaf(fmaf(tz, c.ex, c.cx), ihx, 0.5f * A.nx)), 0), A.nx - 1)
+                                          : ln.a0;
+                        const int b = c.iey != 0.0f
+                                          ? min(max((int)floorf(fmaf(fmaf(tz, c.ey, c.cy), ihy, 0.5f * A.ny)), 0), A.ny - 1)
+                                          : ln.b0;
                         k = min(max(abs(a - ln.a0) + abs(b - ln.b0) - k0, 0), kn - 1);
                         dt = tz - pst[k0 + k];
                     }
@@ -672,11 +691,12 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float
         const int block = (((npairs + npt - 1) / npt + 63) / 64) * 64;
         const int kmax = L.nx + L.ny + 3;
         constexpr size_t budget = 48 * 1024;
-        if (npt <= 8 && sid_runs_lds(64, L.nz, kmax, block / 64) <= budget)
+        const bool fits32 = ((long)L.nx * L.ny * L.nz + (long)L.nz) * 4 < (1L << 31);  // 32-bit byte offsets
+        if (fits32 && npt <= 8 && sid_runs_lds(64, L.nz, kmax, block / 64) <= budget)
             return launch_sid_runs<64>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(64, L.nz, kmax, block / 64));
-        if (npt <= 8 && sid_runs_lds(32, L.nz, kmax, block / 64) <= budget)
+        if (fits32 && npt <= 8 && sid_runs_lds(32, L.nz, kmax, block / 64) <= budget)
             return launch_sid_runs<32>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(32, L.nz, kmax, block / 64));
-        if (npt <= 8 && sid_runs_lds(16, L.nz, kmax, block / 64) <= budget)
+        if (fits32 && npt <= 8 && sid_runs_lds(16, L.nz, kmax, block / 64) <= budget)
             return launch_sid_runs<16>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(16, L.nz, kmax, block / 64));
     }
     const int nchunk = (L.nv + 63) / 64;
