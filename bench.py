@@ -149,7 +149,7 @@ def kernels_only():
     plan.forward_columns(f_cols, out=proj)
     plan.adjoint(y, out=vol, workspace=zws)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": 2 * 4 * a.numel(), "kernels": ["copy", "k_forward", "k_adj_profiles",
+    print(json.dumps({"copy_bytes": 2 * 4 * a.numel(), "kernels": ["copy", "k_forward_runs", "k_adj_profiles",
                                                                     "k_adj_gather_staged"]}))
 
 
@@ -159,8 +159,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=0, metavar="N",
-                    help="also run the serving workload with N requests (256 in the full workload)")
+    ap.add_argument("--serving", type=int, default=32, metavar="N",
+                    help="requests of the serving workload to replay (256 in the full workload; 0: skip)")
     ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (for counters)")
     args = ap.parse_args()
     if args.kernels_only:
@@ -247,6 +247,23 @@ def main():
         e1.record()
     torch.cuda.synchronize()
     tb6 = float(np.mean([a.elapsed_time(b) for a, b in ev6])) * 1e-3
+    # the Siddon pair (exact ray-in-voxel lengths) at the same size
+    sws = torch.empty(max(plan.forward_workspace_bytes(0), plan.adjoint_siddon_workspace_bytes(0)), dtype=torch.uint8,
+                      device=dev)
+    for _ in range(2):
+        plan.forward_siddon(out, out=proj, workspace=sws)
+        plan.adjoint_siddon(Y, out=vol, workspace=sws)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(10)]
+    for e0, e1, e2 in evs:
+        e0.record()
+        plan.forward_siddon(out, out=proj, workspace=sws)
+        e1.record()
+        plan.adjoint_siddon(Y, out=vol, workspace=sws)
+        e2.record()
+    torch.cuda.synchronize()
+    tps = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) * 1e-3
+    tas = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) * 1e-3
+    del sws
     params6, keep6 = plan.solve_params(lam, iters, step1_eq6=True)
     ws6 = torch.empty(plan.reconstruct_workspace_bytes(params6), dtype=torch.uint8, device=dev)
     plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=ws6, step1_eq6=True)
@@ -289,6 +306,7 @@ def main():
         "p_voxel_views_per_s": vv / tp, "pt_voxel_views_per_s": vv / ta,
         "p_ms": tp * 1e3, "pt_ms": ta * 1e3,
         "eq6_backprojector_ms": tb6 * 1e3, "recon_s_step1_eq6": recon6_s,
+        "siddon_p_ms": tps * 1e3, "siddon_pt_ms": tas * 1e3,
         "roofline": roofline,
     }
     if args.serving:
