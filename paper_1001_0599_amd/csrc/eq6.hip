@@ -9,6 +9,9 @@
 // One thread per voxel column segment of 16 z cells, x fastest (lanes of a wave sample
 // neighbouring detector columns, which the caches serve): per view the column's u* terms are
 // computed once and each cell adds its v* row pair; all views in registers, one write per voxel.
+// The view's image is read through a raw buffer of its size at non-negative byte offsets: one
+// address per row (the neighbouring column sits 4 bytes further; column -1 is shifted to column 0
+// with its weight), rows clamped into the image with weight 0 outside it.
 #include <hip/hip_runtime.h>
 
 #include "cbct_internal.h"
@@ -35,6 +38,7 @@ __global__ void __launch_bounds__(256)
     const float ipu = 1.0f / A.pu, ipv = 1.0f / A.pv;
     const float sdd2 = A.sdd * A.sdd;
     const long plane = (long)A.nu * A.nv;
+    const int nu4 = A.nu * 4;
     float acc[EQ6_ZC];
 #pragma unroll
     for (int q = 0; q < EQ6_ZC; q++) acc[q] = 0.0f;
@@ -49,11 +53,15 @@ __global__ void __launch_bounds__(256)
         if (i0 < -1 || i0 >= A.nu) continue;
         const float du = fu - fu0;
         const float wu0 = (i0 >= 0) ? 1.0f - du : 0.0f, wu1 = (i0 + 1 < A.nu) ? du : 0.0f;
-        const int ia = max(i0, 0), ib = min(i0 + 1, A.nu - 1);
         const float w2t2 = fmaf(w, w, t * t);
         const float wk = sdd2 * iw * iw * iw;                    // L^3/(L0 l^2) = SDD^2 l / w^3
         const float vstep = A.sdd * iw * ipv;                    // v* in rows per mm of z
-        const float *img = T + view * plane;
+        const __amdgpu_buffer_rsrc_t img = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(T + view * plane), 0, (int)(plane * 4), 0x00020000);
+        // columns i0 and i0 + 1 of a row at byte offsets ob and ob + 4; i0 = -1 becomes column 0
+        // carrying the weight of column i0 + 1 (the column past the last one has weight 0)
+        const int ob = max(i0, 0) * 4;
+        const float cw0 = i0 >= 0 ? wu0 : wu1, cw1 = i0 >= 0 ? wu1 : 0.0f;
 #pragma unroll
         for (int q = 0; q < EQ6_ZC; q++) {
             const float z = fmaf((float)q, A.hz, zc0);
@@ -63,10 +71,13 @@ __global__ void __launch_bounds__(256)
             const float dv = fv - fv0;
             const float wv0 = (j0 >= 0 && j0 < A.nv) ? 1.0f - dv : 0.0f;
             const float wv1 = (j0 + 1 >= 0 && j0 + 1 < A.nv) ? dv : 0.0f;
-            const float *r0 = img + (long)min(max(j0, 0), A.nv - 1) * A.nu;
-            const float *r1 = img + (long)min(max(j0 + 1, 0), A.nv - 1) * A.nu;
-            const float s = wv0 * fmaf(wu0, r0[ia], wu1 * r0[ib]) + wv1 * fmaf(wu0, r1[ia], wu1 * r1[ib]);
-            const float l = sqrtf(fmaf(z, z, w2t2));
+            const int o0 = min(max(j0, 0), A.nv - 1) * nu4 + ob, o1 = min(max(j0 + 1, 0), A.nv - 1) * nu4 + ob;
+            const float r00 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, o0, 0, 0));
+            const float r01 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, o0 + 4, 0, 0));
+            const float r10 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, o1, 0, 0));
+            const float r11 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, o1 + 4, 0, 0));
+            const float s = fmaf(wv0, fmaf(cw0, r00, cw1 * r01), wv1 * fmaf(cw0, r10, cw1 * r11));
+            const float l = __builtin_amdgcn_sqrtf(fmaf(z, z, w2t2));
             acc[q] = fmaf(wk * l, s, acc[q]);
         }
     }

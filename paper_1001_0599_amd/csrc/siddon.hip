@@ -333,11 +333,13 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
         const int K = sid_piece_list(c, A, tin, tout, kmax, pst, pof, tid, nthr, ln);
         __syncthreads();
         // per piece: length and the byte offset of its voxel column; outside the grid, and past the
-        // last piece up to the chunk edge, an offset past the end of the volume (reads 0)
+        // last piece up to the chunk edge, the volume's size: plus a cell's offset that stays past
+        // the end (reads 0) and below 2^31 (the launcher checks the size)
         const int kr = (K + KP - 1) / KP * KP;
+        const int vbytes = A.nx * A.ny * nz * 4;
         for (int k = tid; k < kr; k += nthr) {
             const bool in = k < K && pof[k] >= 0;
-            pk[k] = make_float2(k < K ? pst[k + 1] - pst[k] : 0.0f, __int_as_float(in ? pof[k] * 4 : 0x7fffffff));
+            pk[k] = make_float2(k < K ? pst[k + 1] - pst[k] : 0.0f, __int_as_float(in ? pof[k] * 4 : vbytes));
         }
         const __amdgpu_buffer_rsrc_t vrs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(vol_t), 0, A.nx * A.ny * nz * 4, 0x00020000);
