@@ -47,7 +47,7 @@ class Params(C.Structure):
     _fields_ = [("lam", C.c_double), ("step", C.c_double), ("tv_eps", C.c_double),
                 ("armijo_c", C.c_double), ("backtrack", C.c_double), ("rof_tol", C.c_double),
                 ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int), ("step1_eq6", C.c_int),
-                ("conv_tol", C.c_double)]
+                ("conv_tol", C.c_double), ("projector", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -271,7 +271,7 @@ def bin_detector(Y, factor: int) -> np.ndarray:
 
 
 DEFAULTS = dict(tv_eps=1e-5, armijo_c=0.01, backtrack=0.6, rof_tol=1e-3, rof_max_iter=50, rof_max_backtrack=30,
-                step1_eq6=False, conv_tol=0.0)
+                step1_eq6=False, conv_tol=0.0, projector=0)
 
 
 def _params(lam, step, **kw):
@@ -279,7 +279,7 @@ def _params(lam, step, **kw):
     p.update(kw)
     return Params(float(lam), float(step), p["tv_eps"], p["armijo_c"], p["backtrack"], p["rof_tol"],
                   int(p["rof_max_iter"]), int(p["rof_max_backtrack"]), int(bool(p["step1_eq6"])),
-                  float(p["conv_tol"]))
+                  float(p["conv_tol"]), int(p["projector"]))
 
 
 class Result:

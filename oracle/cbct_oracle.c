@@ -33,7 +33,8 @@
  *     over voxels of (length of S->D inside the cube) x voxel value.  The pieces come from the
  *     sorted parameters at which the segment crosses the grid planes; a piece's voxel is the
  *     one holding its midpoint (cubes half-open on their upper faces: a ray in a face plane
- *     belongs to the cube above it).  Its transpose is the exact matrix transpose.
+ *     belongs to the cube above it).  Its transpose is the exact matrix transpose.  Algorithm A1 can
+ *     run with either pair (params.projector): the data term, the Schur bound and Step 1 then use it.
  *   - Multigrid (Section II.C.3): coarse-to-fine levels, dims halved per level
  *     over the same box, detector binned 2x2 per level, cell-centred trilinear
  *     prolongation (3/4, 1/4 per axis, clamped), restriction = (1/8) Prol^T.
@@ -69,6 +70,8 @@ typedef struct {
     int step1_eq6;        /* 1: Step 1 uses the Eq. 6 backprojector instead of the exact P^T */
     double conv_tol;      /* > 0: a level stops once |E(f_k) - E(f_k-1)| <= conv_tol E(f_k-1) (k >= 1);
                            * its iteration count is then the upper bound */
+    int projector;        /* 0: the trilinear ray sum P and its transpose; 1: Siddon's exact path and its
+                           * transpose (data term, Schur bound and Step 1) */
 } og_params;
 
 typedef struct {
@@ -712,9 +715,19 @@ static void og_rof(const og_geom *g, const double *gg, double *u, const og_param
 /* ---------------------------------------------------------------------------------- */
 /* Algorithm A1 on one grid                                                           */
 /* ---------------------------------------------------------------------------------- */
-static double og_data_term(const og_geom *g, const double *f, const double *Y, double *r) {
+/* the operator pair of the reconstruction */
+static void og_P(const og_geom *g, int projector, const double *f, double *y) {
+    if (projector == 1) orc_forward_siddon(g, f, y);
+    else orc_forward(g, f, y);
+}
+static void og_PT(const og_geom *g, int projector, const double *y, double *f) {
+    if (projector == 1) orc_adjoint_siddon(g, y, f);
+    else orc_adjoint(g, y, f);
+}
+
+static double og_data_term(const og_geom *g, int projector, const double *f, const double *Y, double *r) {
     long nr = og_nray(g);
-    orc_forward(g, f, r);
+    og_P(g, projector, f, r);
     double s = 0.0;
     for (long q = 0; q < nr; q++) {
         r[q] -= Y[q];
@@ -724,7 +737,7 @@ static double og_data_term(const og_geom *g, const double *f, const double *Y, d
 }
 
 /* max(P 1) and max(P^T 1): the Schur bound ||P||_2^2 <= max row sum * max column sum */
-void orc_schur(const og_geom *g, double *max_p1, double *max_pt1) {
+static void og_schur(const og_geom *g, int projector, double *max_p1, double *max_pt1) {
     long nvox = og_nvox(g), nr = og_nray(g);
     double *one_v = (double *)malloc(sizeof(double) * (size_t)nvox);
     double *one_r = (double *)malloc(sizeof(double) * (size_t)nr);
@@ -732,8 +745,8 @@ void orc_schur(const og_geom *g, double *max_p1, double *max_pt1) {
     double *tr = (double *)malloc(sizeof(double) * (size_t)nr);
     for (long v = 0; v < nvox; v++) one_v[v] = 1.0;
     for (long q = 0; q < nr; q++) one_r[q] = 1.0;
-    orc_forward(g, one_v, tr);
-    orc_adjoint(g, one_r, tv);
+    og_P(g, projector, one_v, tr);
+    og_PT(g, projector, one_r, tv);
     double m1 = 0.0, m2 = 0.0;
     for (long q = 0; q < nr; q++) if (tr[q] > m1) m1 = tr[q];
     for (long v = 0; v < nvox; v++) if (tv[v] > m2) m2 = tv[v];
@@ -742,14 +755,18 @@ void orc_schur(const og_geom *g, double *max_p1, double *max_pt1) {
     free(one_v); free(one_r); free(tv); free(tr);
 }
 
+void orc_schur(const og_geom *g, double *max_p1, double *max_pt1) { og_schur(g, 0, max_p1, max_pt1); }
+
 /* step scale of Step 1: g = f - t * kappa0 * P^T r, kappa0 = 2 N_vox / (N_theta N_pix) */
 static double og_kappa0(const og_geom *g) { return 2.0 * (double)og_nvox(g) / (double)og_nray(g); }
 
-double orc_schur_step(const og_geom *g) {
+static double og_schur_step(const og_geom *g, int projector) {
     double a, b;
-    orc_schur(g, &a, &b);
+    og_schur(g, projector, &a, &b);
     return 1.0 / (og_kappa0(g) * a * b);
 }
+
+double orc_schur_step(const og_geom *g) { return og_schur_step(g, 0); }
 
 static void og_energy_push(og_stats *st, double e) {
     if (!st) return;
@@ -771,7 +788,7 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
     int converged = 0;
     for (int k = 0; k < iters; k++) {
         /* Step 1: gradient step on the data term, g = f - t N dD/df */
-        double Dk = og_data_term(g, f, Y, r);
+        double Dk = og_data_term(g, pr->projector, f, Y, r);
         double Ek = Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps);
         og_energy_push(st, Ek);
         /* "until convergence" (Section II.C.3): f_k is final once the energy stalls */
@@ -781,7 +798,7 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
         }
         e_prev = Ek;
         if (pr->step1_eq6) orc_backproject_eq6(g, r, pt);
-        else orc_adjoint(g, r, pt);
+        else og_PT(g, pr->projector, r, pt);
         for (long v = 0; v < nvox; v++) gg[v] = (og_fault == 9) ? f[v] + kappa * pt[v] : f[v] - kappa * pt[v];
         /* Step 2: ROF */
         tc.outer = k;
@@ -790,7 +807,7 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
         for (long v = 0; v < nvox; v++) f[v] = u[v] > 0.0 ? u[v] : 0.0;
     }
     if (st && !converged) {
-        double Dk = og_data_term(g, f, Y, r);
+        double Dk = og_data_term(g, pr->projector, f, Y, r);
         og_energy_push(st, Dk + pr->lambda * orc_tv_energy(g, f, pr->tv_eps));
     }
     free(r); free(pt); free(gg); free(u);
@@ -932,7 +949,7 @@ int orc_reconstruct(const og_geom *g0, int levels, const int *iters, const og_pa
         } else {
             Yl = (double *)Y0;
         }
-        double t = pr->step > 0.0 ? pr->step : orc_schur_step(&gl);
+        double t = pr->step > 0.0 ? pr->step : og_schur_step(&gl, pr->projector);
         if (st && l < 16) st->t_used[l] = t;
         orc_fbs(&gl, Yl, f, iters[l], pr, t, st, l);
         if (Yl != Y0) free(Yl);

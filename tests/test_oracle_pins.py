@@ -403,6 +403,25 @@ def pin_nnls():
     return e < 1e-6 and res.f.min() >= 0.0, e
 
 
+def pin_fbs_siddon():
+    """Algorithm A1 with the Siddon pair: E = D_s + lambda R non-increasing over 20 iterations on the
+    32^3 workload, and with lambda = 0 projected gradient descent reaches scipy's NNLS objective on
+    the slab-clipped ray-in-cube length matrix (1e-6)."""
+    Y = _cube32_data()
+    e = O.reconstruct(G1, Y, 0.05, [20], 1, projector=1).energy
+    viol = float(np.max(np.diff(e) - 1e-9 * e[:-1]))
+    g = dataclasses.replace(G1, nx=4, ny=4, nz=3, hx=4.0, hy=4.0, hz=4.0, nu=8, nv=6, pu=3.0, pv=3.0, n_views=8)
+    A = brute.cube_lengths(g)
+    rng = np.random.default_rng(17)
+    ftrue = np.maximum(rng.standard_normal(g.n_vox), 0.0) * 0.02
+    Yb = A @ ftrue + 0.01 * rng.standard_normal(A.shape[0])
+    xs, _ = nnls(A, Yb, maxiter=10000)
+    d_star = np.mean((A @ xs - Yb) ** 2)
+    res = O.reconstruct(g, Yb.reshape(g.proj_shape), 0.0, [16000], 1, projector=1)
+    en = abs(np.mean((A @ res.f.ravel() - Yb) ** 2) - d_star) / d_star
+    return viol <= 0 and e[-1] < 0.01 * e[0] and en < 1e-6 and res.f.min() >= 0.0, (viol, e[0], e[-1], en)
+
+
 def pin_resume():
     """10 + 10 outer iterations through d_init equal 20 iterations (oracle: 1e-15)."""
     Y = _cube32_data()
@@ -429,7 +448,7 @@ def pin_constants():
 PINS = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_chords, pin_mass, pin_box,
         pin_centroid, pin_continuum_adjoint, pin_eq6_affine, pin_eq6_near_adjoint, pin_tv_gradient, pin_tv_closed_forms, pin_transfers,
         pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants, pin_convergence_rule,
-        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_sampled, pin_siddon_chords]
+        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_sampled, pin_siddon_chords, pin_fbs_siddon]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
