@@ -264,17 +264,24 @@ def main():
     tps = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) * 1e-3
     tas = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) * 1e-3
     del sws
-    params6, keep6 = plan.solve_params(lam, iters, step1_eq6=True)
-    ws6 = torch.empty(plan.reconstruct_workspace_bytes(params6), dtype=torch.uint8, device=dev)
-    plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=ws6, step1_eq6=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n6 = max(1, min(args.steps, 3))
-    for _ in range(n6):
-        plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=ws6, step1_eq6=True)
-    torch.cuda.synchronize()
-    recon6_s = (time.perf_counter() - t0) / n6
-    del ws6
+    def recon_variant(**kw):
+        """Seconds per reconstruction with other solver options (a warm-up call caches the
+        pair's Schur step first)."""
+        params, keep = plan.solve_params(lam, iters, **kw)
+        wsv = torch.empty(plan.reconstruct_workspace_bytes(params), dtype=torch.uint8, device=dev)
+        plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=wsv, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = max(1, min(args.steps, 3))
+        for _ in range(n):
+            plan.reconstruct(Y, lam=lam, iters=iters, out=out, workspace=wsv, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    log("reconstruction variants: Eq. 6 Step 1, Siddon pair, Siddon + Eq. 6")
+    recon6_s = recon_variant(step1_eq6=True)
+    recon_sid_s = recon_variant(projector=1)
+    recon_sid6_s = recon_variant(projector=1, step1_eq6=True)
     vv = g.n_vox * g.n_views
     # algorithmic bytes per launch: the volume read (P) or written (P^T) once per view, plus the
     # detector samples in and out (4 B each)
@@ -307,6 +314,7 @@ def main():
         "p_ms": tp * 1e3, "pt_ms": ta * 1e3,
         "eq6_backprojector_ms": tb6 * 1e3, "recon_s_step1_eq6": recon6_s,
         "siddon_p_ms": tps * 1e3, "siddon_pt_ms": tas * 1e3,
+        "recon_s_siddon_pair": recon_sid_s, "recon_s_siddon_p_eq6_step1": recon_sid6_s,
         "roofline": roofline,
     }
     if args.serving:

@@ -155,7 +155,11 @@ cbct_status cbct_adjoint(const cbct_plan *plan, int level, const float *d_proj, 
  *   Step 3  f = max(u, 0)
  * Levels run from params.levels-1 (coarsest, started from 0 or from d_init restricted) to 0,
  * each started from the prolonged solution of the coarser one; t = params.step, or when
- * step <= 0 the Schur bound 1 / (kappa0 max(P_l 1) max(P_l^T 1)) per level (cached in the plan). */
+ * step <= 0 the Schur bound 1 / (kappa0 max(P_l 1) max(P_l^T 1)) per level (cached in the plan).
+ * params.projector picks the pair P, P^T: the trilinear sampling pair (Eq. 4 and its exact
+ * adjoint) or the Siddon pair of exact ray-in-voxel lengths (Section II.C.1), everywhere in the
+ * loop (residual, Step 1 and the Schur bound); Siddon with step1_eq6 is the projector and
+ * backprojector pair the paper runs. */
 typedef struct {
     double lambda;          /* TV weight, >= 0 (1/mu of Eq. 2) */
     const int *iters;       /* iters[l]: outer iterations at level l (l = 0 finest), params.levels entries */
@@ -176,6 +180,9 @@ typedef struct {
                              * the first k >= 1 with |E(f_k) - E(f_k-1)| <= conv_tol E(f_k-1), iters[l]
                              * being the upper bound (one more stream synchronisation per outer
                              * iteration); 0 (default): exactly iters[l] iterations */
+    int projector;          /* 0 (default): trilinear P and its adjoint; 1: Siddon P_s and P_s^T (the
+                             * workspace then holds the P_s^T profile tables of the largest level,
+                             * cbct_adjoint_siddon_workspace_size); other values: INVALID_ARG */
 } cbct_solve_params;
 
 /* Optional diagnostics; arrays are caller-owned and may be NULL (lengths may exceed capacities:

@@ -40,7 +40,7 @@ class SolveParams(C.Structure):
                 ("tv_eps", C.c_double), ("armijo_c", C.c_double), ("backtrack", C.c_double),
                 ("rof_tol", C.c_double), ("rof_max_iter", C.c_int), ("rof_max_backtrack", C.c_int),
                 ("replay", C.POINTER(C.c_int)), ("replay_len", C.c_int), ("step1_eq6", C.c_int),
-                ("conv_tol", C.c_double)]
+                ("conv_tol", C.c_double), ("projector", C.c_int)]
 
 
 class SolveStats(C.Structure):

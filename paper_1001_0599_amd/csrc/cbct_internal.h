@@ -90,7 +90,8 @@ struct Level {
     int adj_vsplit = 1;           // view groups of the staged gather
     long adj_part_off = 0;        // float offset of the view-group partial volumes
     ZIndex *d_zix = nullptr;      // [nviews][nu]
-    double schur_t = 0.0;  // cached Schur-bound step (0: not computed yet)
+    double schur_t = 0.0;         // cached Schur-bound step of the trilinear pair (0: not computed yet)
+    double schur_t_siddon = 0.0;  // the same for the Siddon pair
     // device tables
     ColParams *d_cols = nullptr;   // [nviews][nu]
     ViewParams *d_views = nullptr; // [nviews]
@@ -130,10 +131,14 @@ cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const
 // out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
                                 float *out, float *Zws, hipStream_t s, bool preweighted = false);
-// Siddon pair: out = P_s vol_t (vol_t in the column-major layout) and out = P_s^T proj.
-cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float *out, hipStream_t s);
+// Siddon pair: out = P_s vol_t (vol_t in the column-major layout), or with y_sub the residual
+// out = P_s vol_t - y_sub and partials[view * nu + i] = sum of its squares; out = P_s^T proj, or
+// f_base - kappa P_s^T proj.
+cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, const float *y_sub, float *out,
+                                       double *partials, hipStream_t s);
 // P_s^T through per-piece z profiles in ws (cbct_adjoint_siddon_ws_bytes), or the per-cell gather
-cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, void *ws, hipStream_t s);
+cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const float *f_base, float kappa, float *out,
+                                       void *ws, hipStream_t s);
 size_t cbct_adjoint_siddon_ws_bytes(const Level &L);
 
 // ---- solver pieces --------------------------------------------------------------------------

@@ -336,7 +336,7 @@ extern "C" cbct_status cbct_forward_siddon(const cbct_plan *p, int level, const 
     hipStream_t st = (hipStream_t)stream;
     s = cbct_launch_to_columns(L, d_vol, (float *)d_ws, st);
     if (s) return s;
-    return cbct_launch_forward_siddon(L, (const float *)d_ws, d_proj, st);
+    return cbct_launch_forward_siddon(L, (const float *)d_ws, nullptr, d_proj, nullptr, st);
 }
 
 extern "C" cbct_status cbct_adjoint_siddon_workspace_size(const cbct_plan *p, int level, size_t *bytes) {
@@ -358,7 +358,7 @@ extern "C" cbct_status cbct_adjoint_siddon(const cbct_plan *p, int level, const 
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: workspace %zu < %zu bytes", ws_bytes, need);
     if (((uintptr_t)d_ws & 255) != 0)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: workspace must be 256-byte aligned");
-    return cbct_launch_adjoint_siddon(L, d_proj, d_vol, d_ws, (hipStream_t)stream);
+    return cbct_launch_adjoint_siddon(L, d_proj, nullptr, 0.0f, d_vol, d_ws, (hipStream_t)stream);
 }
 
 extern "C" cbct_status cbct_backproject_eq6(const cbct_plan *p, int level, const float *d_proj, float *d_vol,

@@ -132,6 +132,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward(const float *__restrict_
 
 __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__ proj, const SidCol *__restrict__ cols,
                                                        const ViewParams *__restrict__ views, SidArgs A,
+                                                       const float *__restrict__ fbase, float kappa,
                                                        float *__restrict__ out) {
     const int ntx = (A.nx + 15) / 16, nzc = (A.nz + SID_TZ - 1) / SID_TZ;
     int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
@@ -207,7 +208,10 @@ __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__
     const long plane = (long)A.nx * A.ny;
 #pragma unroll
     for (int k = 0; k < SID_TZ; k++)
-        if (c0 + k < A.nz) out[(c0 + k) * plane + (long)b * A.nx + a] = acc[k];
+        if (c0 + k < A.nz) {
+            const long o = (c0 + k) * plane + (long)b * A.nx + a;
+            out[o] = fbase ? fmaf(-kappa, acc[k], fbase[o]) : acc[k];
+        }
 }
 
 // Siddon forward by runs.  The xy line of a detector column is cut by the x and y grid planes
@@ -304,7 +308,8 @@ __device__ int sid_piece_list(const SidCol &c, const SidArgs &A, float tin, floa
 template <int KP, int NPT>
 __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__restrict__ vol_t,
                                                              const SidCol *__restrict__ cols, SidArgs A, int kmax,
-                                                             float *__restrict__ out) {
+                                                             const float *__restrict__ ysub, float *__restrict__ out,
+                                                             double *__restrict__ partials) {
     extern __shared__ float4 lds4[];
     constexpr int S = KP + 1;  // per cell: (Q at piece start, piece value) for KP pieces, then (chunk total, 0)
     const int nz = A.nz;
@@ -449,6 +454,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
             }
         }
     }
+    double part = 0.0;
 #pragma unroll
     for (int p = 0; p < NPT; p++) {
         const int j = tid + p * nthr;
@@ -456,8 +462,27 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
             const int jm = A.nv - 1 - j;
             const float kz = sid_row_v(j, A) * c.ilxy;
             const float w = sqrtf(fmaf(kz, kz, 1.0f));  // the mirror's weight is the same
-            out[((long)view * A.nv + j) * A.nu + i] = acc[p] * w;
-            if (jm != j) out[((long)view * A.nv + jm) * A.nu + i] = accm[p] * w;
+            const long o1 = ((long)view * A.nv + j) * A.nu + i, o2 = ((long)view * A.nv + jm) * A.nu + i;
+            float r1 = acc[p] * w, r2 = accm[p] * w;
+            if (ysub) {  // residual and its sum of squares
+                r1 -= ysub[o1];
+                r2 -= ysub[o2];
+                part += (double)r1 * (double)r1;
+                if (jm != j) part += (double)r2 * (double)r2;
+            }
+            out[o1] = r1;
+            if (jm != j) out[o2] = r2;
+        }
+    }
+    if (partials) {
+        __shared__ double wsum[4];
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        if (lane == 0) wsum[wave] = part;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w2 = 0; w2 < nw; w2++) sum += wsum[w2];
+            partials[vc] = sum;
         }
     }
 }
@@ -598,6 +623,7 @@ constexpr int SGC = 16;
 __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restrict__ Z, const int4 *__restrict__ rec,
                                                            const SidCol *__restrict__ cols,
                                                            const ViewParams *__restrict__ views, SidArgs A, int kmax,
+                                                           const float *__restrict__ fbase, float kappa,
                                                            float *__restrict__ out) {
     const int ntx = (A.nx + 7) / 8;
     const int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
@@ -654,7 +680,30 @@ __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restri
     const long plane = (long)A.nx * A.ny;
 #pragma unroll
     for (int u = 0; u < SGC; u++)
-        if (c0 + u < nz) out[(c0 + u) * plane + (long)b * A.nx + a] = acc[u];
+        if (c0 + u < nz) {
+            const long o = (c0 + u) * plane + (long)b * A.nx + a;
+            out[o] = fbase ? fmaf(-kappa, acc[u], fbase[o]) : acc[u];
+        }
+}
+
+// residual of the per-ray forward: one work-group per detector column, out = out - ysub in
+// place and partials[view * nu + i] = sum over the column's rows of its square
+__global__ void __launch_bounds__(256) k_sid_residual(const float *__restrict__ ysub, float *__restrict__ out,
+                                                      double *__restrict__ partials, int nu, int nv) {
+    __shared__ double wsum[4];
+    const long vc = blockIdx.x;
+    const long view = vc / nu, i = vc - view * nu;
+    double part = 0.0;
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+        const long o = (view * nv + j) * nu + i;
+        const float r = out[o] - ysub[o];
+        out[o] = r;
+        part += (double)r * (double)r;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0 && partials) partials[vc] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 SidArgs sid_args(const Level &L) {
@@ -668,23 +717,24 @@ SidArgs sid_args(const Level &L) {
 }  // namespace
 
 template <int KP>
-cbct_status launch_sid_runs(const Level &L, const float *vol_t, float *out, hipStream_t s, int npt, int block,
-                            int kmax, size_t lds) {
+cbct_status launch_sid_runs(const Level &L, const float *vol_t, const float *ysub, float *out, double *partials,
+                            hipStream_t s, int npt, int block, int kmax, size_t lds) {
     const dim3 grid((unsigned)((long)L.nviews * L.nu));
     if (npt == 1)
-        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 1>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, out);
+        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 1>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, ysub, out, partials);
     else if (npt == 2)
-        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 2>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, out);
+        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 2>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, ysub, out, partials);
     else if (npt == 4)
-        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 4>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, out);
+        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 4>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, ysub, out, partials);
     else
-        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 8>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, out);
+        hipLaunchKernelGGL((k_siddon_forward_runs<KP, 8>), grid, dim3(block), lds, s, vol_t, L.d_sid, sid_args(L), kmax, ysub, out, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_siddon_forward_runs launch");
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float *out, hipStream_t s) {
+cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, const float *ysub, float *out,
+                                       double *partials, hipStream_t s) {
     {
         // the run-summing kernel when its tables fit: rays in mirrored pairs, up to 256 threads
         const int npairs = (L.nv + 1) / 2;
@@ -695,11 +745,14 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float
         constexpr size_t budget = 48 * 1024;
         const bool fits32 = ((long)L.nx * L.ny * L.nz + (long)L.nz) * 4 < (1L << 31);  // 32-bit byte offsets
         if (fits32 && npt <= 8 && sid_runs_lds(64, L.nz, kmax, block / 64) <= budget)
-            return launch_sid_runs<64>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(64, L.nz, kmax, block / 64));
+            return launch_sid_runs<64>(L, vol_t, ysub, out, partials, s, npt, block, kmax,
+                                         sid_runs_lds(64, L.nz, kmax, block / 64));
         if (fits32 && npt <= 8 && sid_runs_lds(32, L.nz, kmax, block / 64) <= budget)
-            return launch_sid_runs<32>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(32, L.nz, kmax, block / 64));
+            return launch_sid_runs<32>(L, vol_t, ysub, out, partials, s, npt, block, kmax,
+                                         sid_runs_lds(32, L.nz, kmax, block / 64));
         if (fits32 && npt <= 8 && sid_runs_lds(16, L.nz, kmax, block / 64) <= budget)
-            return launch_sid_runs<16>(L, vol_t, out, s, npt, block, kmax, sid_runs_lds(16, L.nz, kmax, block / 64));
+            return launch_sid_runs<16>(L, vol_t, ysub, out, partials, s, npt, block, kmax,
+                                         sid_runs_lds(16, L.nz, kmax, block / 64));
     }
     const int nchunk = (L.nv + 63) / 64;
     const long items = (long)L.nviews * L.nu * nchunk;
@@ -709,6 +762,12 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, float
                        out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_siddon_forward launch");
+    if (ysub) {
+        hipLaunchKernelGGL(k_sid_residual, dim3((unsigned)((long)L.nviews * L.nu)), dim3(256), 0, s, ysub, out, partials,
+                           L.nu, L.nv);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cbct_hip_error(e, "k_sid_residual launch");
+    }
     return CBCT_OK;
 }
 
@@ -718,7 +777,8 @@ size_t cbct_adjoint_siddon_ws_bytes(const Level &L) {
     return ((lines * kmax * L.nz * 4 + 255) & ~(size_t)255) + lines * 16;
 }
 
-cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float *out, void *ws, hipStream_t s) {
+cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
+                                       void *ws, hipStream_t s) {
     const int kmax = L.nx + L.ny + 3;
     const size_t lds = (size_t)(3 * L.nv + 1) * 4 + (size_t)(kmax + 1) * 4 + (size_t)4 * 64 * (16 + 1) * 4;
     if (lds <= 64 * 1024) {
@@ -731,7 +791,7 @@ cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float 
         if (e != hipSuccess) return cbct_hip_error(e, "k_sid_profiles launch");
         const dim3 grid((unsigned)(((L.nx + 7) / 8) * ((L.ny + 7) / 8)), (unsigned)((L.nz + 4 * SGC - 1) / (4 * SGC)));
         hipLaunchKernelGGL(k_sid_gather_pieces, grid, dim3(256), 0, s, Z, rec, L.d_sid, L.d_views, sid_args(L), kmax,
-                           out);
+                           fbase, kappa, out);
         e = hipGetLastError();
         if (e != hipSuccess) return cbct_hip_error(e, "k_sid_gather_pieces launch");
         return CBCT_OK;
@@ -739,7 +799,7 @@ cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, float 
     const long blocks = (long)((L.nx + 15) / 16) * ((L.ny + 15) / 16) * ((L.nz + SID_TZ - 1) / SID_TZ);
     if (blocks > 0x7fffffffL) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: grid too large");
     hipLaunchKernelGGL(k_siddon_gather, dim3((unsigned)blocks), dim3(256), 0, s, proj, L.d_sid, L.d_views, sid_args(L),
-                       out);
+                       fbase, kappa, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_siddon_gather launch");
     return CBCT_OK;

@@ -1,7 +1,7 @@
 // Reconstruction driver: Algorithm A1 of the paper (Section II.B) on every multigrid level
 // (Section II.C.3), with Step 2 solved by gradient descent and the Armijo rule (Eq. 5).
 //
-// Per outer iteration, on the caller's stream:
+// Per outer iteration, on the caller's stream (P, P^T: the trilinear pair or the Siddon pair):
 //   P f - Y_l (residual epilogue of the projector)          -> r
 //   g = f - kappa P^T r (epilogue of the adjoint gather)     Step 1, kappa = t * 2 N_vox / N_rays
 //   u = g; ROF iterations: gradient pass, trial pass (4 step sizes), decision kernel, update
@@ -76,7 +76,7 @@ size_t partial_count(const cbct_plan *p) {
     return m;
 }
 
-Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws) {
+Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws, int projector = 0) {
     Carver c{(char *)ws};
     const Level &L0 = p->lv[0];
     Bufs b{};
@@ -86,9 +86,11 @@ Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws) {
     b.u = c.take<float>(L0.nvox());
     b.d = c.take<float>(L0.nvox());
     b.r = c.take<float>(std::max(L0.nray(), L0.nvox()));
-    long zf = 0;
-    for (int l = 0; l < levels; l++) zf = std::max(zf, p->lv[l].z_floats);
-    b.z = c.take<float>((size_t)zf);
+    // the adjoint's scratch: the trilinear pair's Z tables, or the Siddon pair's profile tables
+    size_t zb = 0;
+    for (int l = 0; l < levels; l++)
+        zb = std::max(zb, projector == 1 ? cbct_adjoint_siddon_ws_bytes(p->lv[l]) : (size_t)p->lv[l].z_floats * 4);
+    b.z = reinterpret_cast<float *>(c.take<char>(zb));
     for (int l = 0; l < 8; l++) b.ypyr[l] = nullptr;
     for (int l = 1; l < levels; l++)
         if (p->bin_detector) b.ypyr[l] = c.take<float>(p->lv[l].nray());
@@ -114,6 +116,8 @@ cbct_status check_params(const cbct_plan *p, const cbct_solve_params *pr, const 
     if (pr->replay_len < 0 || (pr->replay_len > 0 && !pr->replay))
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: replay_len > 0 needs a replay array", who);
     if (!(pr->conv_tol >= 0.0)) return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: conv_tol < 0", who);
+    if (pr->projector != 0 && pr->projector != 1)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "%s: projector %d is neither 0 nor 1", who, pr->projector);
     return CBCT_OK;
 }
 
@@ -123,22 +127,27 @@ int energy_slots(const cbct_solve_params *pr) {
     return n;
 }
 
-// Schur bound t = 1 / (kappa0 max(P 1) max(P^T 1)), cached per plan level
-cbct_status schur_step(cbct_plan *p, int level, const Bufs &b, hipStream_t s, double *t_out) {
+// Schur bound t = 1 / (kappa0 max(P 1) max(P^T 1)), cached per plan level and projector pair
+cbct_status schur_step(cbct_plan *p, int level, int projector, const Bufs &b, hipStream_t s, double *t_out) {
     Level &L = p->lv[level];
+    double &cached = projector == 1 ? L.schur_t_siddon : L.schur_t;
     {
         std::lock_guard<std::mutex> lk(g_schur_mu);
-        if (L.schur_t > 0.0) {
-            *t_out = L.schur_t;
+        if (cached > 0.0) {
+            *t_out = cached;
             return CBCT_OK;
         }
     }
     cbct_status st;
     if ((st = cbct_launch_fill(b.ft, L.nvox(), 1.0f, s))) return st;
-    if ((st = cbct_launch_forward(L, b.ft, nullptr, b.r, nullptr, s))) return st;
+    st = projector == 1 ? cbct_launch_forward_siddon(L, b.ft, nullptr, b.r, nullptr, s)
+                        : cbct_launch_forward(L, b.ft, nullptr, b.r, nullptr, s);
+    if (st) return st;
     if ((st = cbct_launch_max(b.r, L.nray(), b.part, b.sums, s))) return st;
     if ((st = cbct_launch_fill(b.r, L.nray(), 1.0f, s))) return st;
-    if ((st = cbct_launch_adjoint(L, b.r, nullptr, 0.0f, b.u, b.z, s))) return st;
+    st = projector == 1 ? cbct_launch_adjoint_siddon(L, b.r, nullptr, 0.0f, b.u, b.z, s)
+                        : cbct_launch_adjoint(L, b.r, nullptr, 0.0f, b.u, b.z, s);
+    if (st) return st;
     if ((st = cbct_launch_max(b.u, L.nvox(), b.part, b.sums + 1, s))) return st;
     double mx[2];
     CBCT_HIP(hipMemcpyAsync(mx, b.sums, sizeof(mx), hipMemcpyDeviceToHost, s));
@@ -148,8 +157,8 @@ cbct_status schur_step(cbct_plan *p, int level, const Bufs &b, hipStream_t s, do
     if (!(lip > 0.0) || !std::isfinite(lip))
         return cbct_set_error(CBCT_ERR_NONFINITE, "level %d: Schur bound %g is not positive and finite", level, lip);
     std::lock_guard<std::mutex> lk(g_schur_mu);
-    L.schur_t = 1.0 / lip;
-    *t_out = L.schur_t;
+    cached = 1.0 / lip;
+    *t_out = cached;
     return CBCT_OK;
 }
 
@@ -251,7 +260,7 @@ extern "C" cbct_status cbct_reconstruct_workspace_size(const cbct_plan *p, const
     cbct_status st = check_params(p, pr, "reconstruct_workspace_size");
     if (st) return st;
     if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct_workspace_size: NULL out");
-    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr).bytes;
+    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr, pr->projector).bytes;
     return CBCT_OK;
 }
 
@@ -264,7 +273,8 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
     if (!d_y || !d_out || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: NULL pointer");
     const int levels = pr->levels;
     const int nslots = energy_slots(pr);
-    Bufs b = carve(p, levels, nslots, d_ws);
+    const int proj = pr->projector;
+    Bufs b = carve(p, levels, nslots, d_ws, proj);
     if (ws_bytes < b.bytes)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: workspace %zu < %zu bytes", ws_bytes, b.bytes);
     if (((uintptr_t)d_ws & 255) != 0)
@@ -313,7 +323,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         }
         double t = pr->step;
         if (!(t > 0.0))
-            if ((st = schur_step(p, l, b, s, &t))) return st;
+            if ((st = schur_step(p, l, proj, b, s, &t))) return st;
         if (stats) stats->t_used[l] = t;
         const float kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
         if ((st = cbct_launch_to_columns(L, b.f, b.ft, s))) return st;
@@ -321,9 +331,12 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         for (int k = 0; k <= pr->iters[l]; k++) {
             const bool last = (k == pr->iters[l]);
             if (last && !want_energy) break;
-            // residual r = P f - Y_l (ray-weighted for the exact adjoint) and its sum of squares
+            // residual r = P f - Y_l and its sum of squares (the trilinear pair hands its exact
+            // adjoint the ray-weighted residual)
             const bool eq6 = pr->step1_eq6 != 0;
-            if ((st = cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s, !eq6))) return st;
+            st = proj == 1 ? cbct_launch_forward_siddon(L, b.ft, Yl, b.r, b.part, s)
+                           : cbct_launch_forward(L, b.ft, Yl, b.r, b.part, s, !eq6);
+            if (st) return st;
             if (want_energy || conv) {
                 if ((st = cbct_launch_sum_rows(b.part, L.nviews * L.nu, 1, b.eng + 2 * eslot, s))) return st;
                 if ((st = cbct_launch_tv_energy(L, pr->tv_eps, b.f, b.part, b.eng + 2 * eslot + 1, s))) return st;
@@ -343,11 +356,13 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             }
             if (last) break;
             // Step 1: g = f - kappa P^T r, or with the Eq. 6 backprojector in place of P^T
-            if (eq6) {
-                if ((st = cbct_launch_backproject_eq6(L, b.r, b.f, kappa, b.g, s))) return st;
-            } else if ((st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true))) {
-                return st;
-            }
+            if (eq6)
+                st = cbct_launch_backproject_eq6(L, b.r, b.f, kappa, b.g, s);
+            else if (proj == 1)
+                st = cbct_launch_adjoint_siddon(L, b.r, b.f, kappa, b.g, b.z, s);
+            else
+                st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true);
+            if (st) return st;
             // Step 2
             if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
             // Step 3

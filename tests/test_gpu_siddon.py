@@ -2,6 +2,8 @@
 
 Bar: relative L2 <= 1e-4 (FP32 crossing parameters vs FP64 sorted crossings); at full size on
 sampled rays and voxels that the oracle computes one by one, plus the adjoint identity."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -90,6 +92,25 @@ def test_siddon_full_size_adjoint_identity():
         b = torch.sum(x.double() * plan.adjoint_siddon(y).double()).item()
         scale = abs(a) if kind == "uniform" else (torch.linalg.norm(px) * torch.linalg.norm(y.double())).item()
         assert abs(a - b) / scale < tol, (kind, a, b)
+
+
+# a tall thin volume seen by 2048 detector rows: rays enter and leave through the top and bottom
+# faces, 352 z cells are too many for the run-summing projector's tables (per-ray walk)
+TALL = dataclasses.replace(CASES["cube32"], nx=8, ny=8, nz=352, hx=2.0, hy=2.0, hz=0.25, nu=16, nv=2048, pu=2.0,
+                           pv=0.08, n_views=4, angles=(0.1, 0.9, 2.0, 2.6))
+
+
+def test_siddon_tall_volume():
+    g = TALL
+    announce("siddon pair on a tall 8x8x352 volume, 2048 rows")
+    plan = _plan(g)
+    x = S.voxelize(g, S.make_phantom(g, 41), 1) + 0.01 * S.random_volume(g, 43, "normal")
+    e = rel_l2(to_np(plan.forward_siddon(to_gpu(x))), O.forward_siddon(g, x))
+    assert e < TOL, ("forward", e)
+    for seed, kind in ((44, "uniform"), (45, "normal")):
+        y = S.random_projections(g, seed, kind)
+        e = rel_l2(to_np(plan.adjoint_siddon(to_gpu(y))), O.adjoint_siddon(g, y))
+        assert e < TOL, ("adjoint", kind, e)
 
 
 def test_siddon_deterministic_and_validation():

@@ -90,13 +90,23 @@ def _compare_solve(g, Y, lam, iters, levels, step=0.0, **kw):
     q = _first_divergence(st["trace"], res.trace)
     replayed = False
     if q is not None:
-        # the oracle's margin at the first differing decision must be an FP32 tie
-        e0, enew, G = res.rof_e[q]
-        m = res.trace[q][3]
-        t = res.t_used[res.trace[q][0]]
-        armijo = abs((e0 - 0.01 * t * 0.6 ** max(m, 0) * G) - enew) / e0
-        stop = abs(abs(enew - e0) / e0 - 1e-3) / 1e-3
-        assert min(armijo, stop) < 1e-4, ("decision diverged with a large margin", q, st["trace"][q], res.trace[q])
+        # the oracle's margin at the first differing decision must be an FP32 tie: the Armijo
+        # test of record q, or the stop test of record q - 1 when one side ended the outer
+        # iteration there and the other went on
+        margins = []
+        if q < len(res.trace):
+            e0, enew, G = res.rof_e[q]
+            m = res.trace[q][3]
+            t = res.t_used[res.trace[q][0]]
+            margins.append(abs((e0 - 0.01 * t * 0.6 ** max(m, 0) * G) - enew) / e0)
+            margins.append(abs(abs(enew - e0) / e0 - 1e-3) / 1e-3)
+        if q > 0:
+            e0, enew, _ = res.rof_e[q - 1]
+            margins.append(abs(abs(enew - e0) / e0 - 1e-3) / 1e-3)
+        assert min(margins) < 1e-4, ("decision diverged with a large margin", q, margins,
+                                     st["trace"][q] if q < len(st["trace"]) else None,
+                                     res.trace[q] if q < len(res.trace) else None,
+                                     rel_l2(got, res.f))
         f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True,
                                  replay=[int(r[3]) for r in res.trace], **kw)
         got = to_np(f)
@@ -123,6 +133,89 @@ def test_reconstruct_eq6_step1_matches_oracle():
     e, replayed, res, st = _compare_solve(G1, Y, 0.05, [20], 1, step1_eq6=True)
     assert e < 1e-3, (e, replayed)
     assert rel_l2(st["energy"], res.energy) < 1e-4
+
+
+def test_reconstruct_siddon_matches_oracle():
+    """Algorithm A1 with the Siddon pair (exact ray-in-voxel lengths) as P and P^T.  The plan
+    runs the trilinear pair first, so the two pairs' cached Schur steps must stay apart."""
+    announce("reconstruct 32^3, 16 views, 20 iterations, Siddon pair")
+    Y = _cube32_y()
+    plan = _plan(G1)
+    _, st0 = plan.reconstruct(to_gpu(Y), lam=0.05, iters=[2], stats=True)
+    e, replayed, res, st = _compare_solve(G1, Y, 0.05, [20], 1, projector=1)
+    assert e < 1e-3, (e, replayed)
+    assert abs(st["t_used"][0] - res.t_used[0]) / res.t_used[0] < 1e-5
+    assert rel_l2(st["energy"], res.energy) < 1e-4
+    _, st1 = plan.reconstruct(to_gpu(Y), lam=0.05, iters=[2], stats=True, projector=1)
+    assert st1["t_used"][0] == pytest.approx(res.t_used[0], rel=1e-5)
+    assert abs(st0["t_used"][0] - st1["t_used"][0]) > 1e-3 * st1["t_used"][0]
+
+
+def test_reconstruct_siddon_eq6_matches_oracle():
+    """The pair the paper runs: Siddon P in the residual, the Eq. 6 backprojector in Step 1."""
+    announce("reconstruct 32^3, 16 views, 20 iterations, Siddon P + Eq. 6 Step 1")
+    Y = _cube32_y()
+    e, replayed, res, st = _compare_solve(G1, Y, 0.05, [20], 1, projector=1, step1_eq6=True)
+    assert e < 1e-3, (e, replayed)
+    assert rel_l2(st["energy"], res.energy) < 1e-4
+
+
+def test_reconstruct_siddon_two_levels():
+    """Two multigrid levels (binned detector) with the Siddon pair on the quarter-size workload."""
+    announce("reconstruct 128x128x16, 40 views, 2 levels, Siddon pair")
+    ph = S.make_phantom(G2Q, 31)
+    Y = S.poisson_log(S.analytic_projections(G2Q, ph), 1e5, 32)
+    e, replayed, res, st = _compare_solve(G2Q, Y, 0.05, [6, 4], 2, projector=1)
+    assert e < 1e-3, (e, replayed)
+
+
+def test_reconstruct_siddon_tall_volume():
+    """A tall thin volume (352 z cells): too many for the run-summing Siddon projector's
+    tables, so the residual takes the per-ray walk and its separate residual pass.  Four views
+    of an 8 x 8 footprint make this solve ill-conditioned: the FP32 crossings (about 1e-5 off
+    the FP64 ones for these nearly horizontal rays) grow to 9e-5 in f after 3 outer iterations
+    and to 2e-3 after 5, where a Step 2 stop test then falls the other way; so 3 iterations."""
+    g = dataclasses.replace(G1, nx=8, ny=8, nz=352, hx=2.0, hy=2.0, hz=0.25, nu=16, nv=2048, pu=2.0, pv=0.08,
+                            n_views=4, angles=(0.1, 0.9, 2.0, 2.6))
+    announce("reconstruct 8x8x352, 4 views x 2048 rows, Siddon pair (per-ray residual)")
+    ph = S.make_phantom(g, 41)
+    Y = S.poisson_log(S.analytic_projections(g, ph), 1e5, 42)
+    e, replayed, res, st = _compare_solve(g, Y, 0.05, [3], 1, projector=1)
+    assert e < 1e-3, (e, replayed)
+    assert rel_l2(st["energy"], res.energy) < 1e-4
+
+
+def test_reconstruct_siddon_long_lines_step1():
+    """Lines too long for the P_s^T profile tables (4096 x 4096 voxels): Step 1 takes the
+    per-cell gather with its f - kappa P_s^T r epilogue.  One outer iteration with a fixed t
+    and no ROF iterations (u = g), from a non-negative start; compared where Step 1 moved f."""
+    g = dataclasses.replace(G1, nx=4096, ny=4096, nz=1, hx=0.1, hy=0.1, hz=0.01, nu=16, nv=2048, pu=0.15, pv=0.01,
+                            n_views=2, angles=(0.3, 1.9))
+    announce("reconstruct step 1, 4096x4096x1, 2 views x 2048 rows, Siddon pair (per-cell gather)")
+    y = S.random_projections(g, 5)
+    f0 = 0.01 * S.random_volume(g, 7)
+    res = O.reconstruct(g, y, 0.05, [1], 1, step=1e-3, rof_max_iter=0, projector=1, d_init=f0)
+    plan = _plan(g)
+    f, st = plan.reconstruct(to_gpu(y), lam=0.05, iters=[1], step=1e-3, init=to_gpu(f0), stats=True,
+                             rof_max_iter=0, projector=1)
+    got = to_np(f).ravel()
+    want, base = res.f.ravel(), f0.ravel()
+    moved = np.flatnonzero(want != base)
+    assert moved.size > 10000
+    assert rel_l2(got[moved] - base[moved], want[moved] - base[moved]) < 1e-3
+    assert rel_l2(st["energy"], res.energy) < 1e-4
+
+
+def test_projector_param_validation():
+    from paper_1001_0599_amd import _lib
+    plan = _plan(G1)
+    params, keep = plan.solve_params(0.05, [1], projector=2)
+    n = _lib.C.c_size_t(0)
+    assert _lib.lib().cbct_reconstruct_workspace_size(plan.handle, _lib.C.byref(params), _lib.C.byref(n)) == 1
+    p0, _ = plan.solve_params(0.05, [1])
+    p1, _ = plan.solve_params(0.05, [1], projector=1)
+    assert plan.reconstruct_workspace_bytes(p1) >= plan.adjoint_siddon_workspace_bytes(0)
+    assert plan.reconstruct_workspace_bytes(p0) > 0
 
 
 @pytest.mark.parametrize("mas", S.CONFIGS["shortscan32"]["mas"])
