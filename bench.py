@@ -25,9 +25,10 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-# HBM traffic of the P^T operator per launch, from hardware counters (FETCH_SIZE and WRITE_SIZE,
-# each scaled by what the counter reads for a plain copy of known size).  The record names the
-# sources it was measured on; it is reported only while they are unchanged.
+# HBM traffic and L2 hit rate of the P^T operator per launch, from hardware counters (FETCH_SIZE
+# and WRITE_SIZE, each scaled by what the counter reads for a plain copy of known size; TCC_HIT and
+# TCC_MISS).  The record names the sources it was measured on; it is reported only while they are
+# unchanged.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "adjoint_traffic_512x512x64_40views.txt")
 TRAFFIC_SOURCES = ["backproject.hip", "cbct_internal.h", "plan.cpp"]
 
@@ -42,19 +43,20 @@ def sources_digest(names):
 
 
 def measured_traffic():
-    """Bytes per launch from the committed counter record, or None if it is missing or stale."""
+    """(HBM bytes per launch, L2 hit rate) of P^T from the committed counter record, or
+    (None, None) if it is missing or stale."""
     try:
         with open(TRAFFIC_RECORD) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
     except OSError:
-        return None
+        return None, None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("sources_sha256") != sources_digest(TRAFFIC_SOURCES):
-        return None
+        return None, None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]), float(kv.get("l2_hit_rate", "nan"))
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 def cpu_baseline(g):
@@ -126,8 +128,10 @@ def serving_run(n_requests):
 
 
 def kernels_only():
-    """One launch each of a plain 256 MB copy, the projector kernel and the adjoint gather at the
-    512x512x64 / 40-view size (driver for hardware-counter runs)."""
+    """One launch each of a plain 256 MB copy and the hot kernels at the 512x512x64 / 40-view size:
+    P (k_forward_runs), P^T (k_adj_profiles + k_adj_gather_staged), the Eq. 6 backprojector, the
+    Siddon pair, and one Step 2 solve (k_tv_grad, k_tv_trial, ...); the driver for hardware-counter
+    runs, whose records `--counter-summary` turns into the traffic and L2 hit-rate table."""
     import torch
 
     import cbct_synth as S
@@ -148,9 +152,143 @@ def kernels_only():
     b.copy_(a)
     plan.forward_columns(f_cols, out=proj)
     plan.adjoint(y, out=vol, workspace=zws)
+    plan.backproject_eq6(y, out=vol)
+    del zws
+    sws = torch.empty(max(plan.forward_workspace_bytes(0), plan.adjoint_siddon_workspace_bytes(0)),
+                      dtype=torch.uint8, device="cuda")
+    fv = f_cols.permute(2, 0, 1).contiguous()
+    plan.forward_siddon(fv, out=proj, workspace=sws)
+    plan.adjoint_siddon(y, out=vol, workspace=sws)
+    del sws
+    plan.tv_prox(fv, 0.05, 1e-3)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": 2 * 4 * a.numel(), "kernels": ["copy", "k_forward_runs", "k_adj_profiles",
-                                                                    "k_adj_gather_staged"]}))
+    print(json.dumps({"copy_bytes": 2 * 4 * a.numel()}))
+
+
+COUNTER_KERNELS = [  # (label, kernel-name prefix) in the order of the table
+    ("device copy (256 MiB, calibration)", "__amd_rocclr_copyBuffer"),
+    ("P: k_forward_runs", "k_forward_runs"),
+    ("P^T pass 1: k_adj_profiles", "k_adj_profiles"),
+    ("P^T pass 2: k_adj_gather_staged", "k_adj_gather_staged"),
+    ("Eq. 6: k_backproject_eq6", "k_backproject_eq6"),
+    ("P_s: k_siddon_forward_runs", "k_siddon_forward_runs"),
+    ("P_s^T pass 1: k_sid_profiles", "k_sid_profiles"),
+    ("P_s^T pass 2: k_sid_gather_pieces", "k_sid_gather_pieces"),
+    ("Step 2: k_tv_grad", "k_tv_grad"),
+    ("Step 2: k_tv_trial", "k_tv_trial"),
+]
+
+
+def read_counters(d, names):
+    """Per kernel and counter, the values of its dispatches (each summed over the counter's
+    instances), from a rocprofv3 output directory (its SQLite database)."""
+    import glob
+    import re
+    import sqlite3
+    from collections import defaultdict
+
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit("no rocprofv3 database under %s" % d)
+    con = sqlite3.connect(dbs[0])
+    per = defaultdict(lambda: defaultdict(float))  # kernel -> dispatch -> sum over the names
+    for disp, kn, cn, v in con.execute(
+            "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+        if cn not in names:
+            continue
+        k = re.sub(r"\(.*", "", kn.replace("void ", "").replace("(anonymous namespace)::", ""))
+        per[(k, cn)][disp] += v
+    return {key: list(by_disp.values()) for key, by_disp in per.items()}
+
+
+def counter_summary(fetch_dir, write_dir, hit_dir):
+    """Print the traffic and L2 hit-rate record (the file TRAFFIC_RECORD holds) from three counter
+    runs of --kernels-only."""
+    F = read_counters(fetch_dir, {"FETCH_SIZE"})
+    W = read_counters(write_dir, {"WRITE_SIZE"})
+    H = read_counters(hit_dir, {"TCC_HIT_sum", "TCC_MISS_sum"})
+
+    def pick(tab, prefix, cn):
+        # the mean over the kernel's dispatches; for the copy, its largest dispatch (the 256 MiB
+        # calibration copy, not the small copies around it)
+        vals = [v for (k, c), v in tab.items() if c == cn and k.startswith(prefix)]
+        if len(vals) != 1:
+            return None
+        return max(vals[0]) if prefix == COUNTER_KERNELS[0][1] else sum(vals[0]) / len(vals[0])
+
+    copy_half = 64 * 2 ** 20 * 4  # bytes the copy reads (and writes)
+    cf = copy_half / (pick(F, COUNTER_KERNELS[0][1], "FETCH_SIZE") * 1024)
+    cw = copy_half / (pick(W, COUNTER_KERNELS[0][1], "WRITE_SIZE") * 1024)
+    rows, got = [], {}
+    for label, pre in COUNTER_KERNELS:
+        fs, ws = pick(F, pre, "FETCH_SIZE"), pick(W, pre, "WRITE_SIZE")
+        hi, mi = pick(H, pre, "TCC_HIT_sum"), pick(H, pre, "TCC_MISS_sum")
+        if fs is None or ws is None:
+            continue
+        gb = (fs * 1024 * cf + ws * 1024 * cw) / 1e9
+        hit = hi / (hi + mi) if hi is not None and mi is not None and hi + mi > 0 else float("nan")
+        got[pre] = (gb, hi or 0.0, mi or 0.0)
+        rows.append("  %-36s %14.1f %14.1f %10.3f %9.1f%%" % (label, fs, ws, gb, 100 * hit))
+    pt_gb = got["k_adj_profiles"][0] + got["k_adj_gather_staged"][0]
+    pt_hit = sum(got[k][1] for k in ("k_adj_profiles", "k_adj_gather_staged"))
+    pt_miss = sum(got[k][2] for k in ("k_adj_profiles", "k_adj_gather_staged"))
+    lines = [
+        "HBM traffic and L2 hit rate per launch from hardware counters, 512x512x64 voxels, 40 views,",
+        "512x384 detector (MI355X, gfx950).  Three rocprofv3 runs of the same program, from the repository root:",
+        "  cd /tmp && export TMPDIR=/tmp",
+        "  rocprofv3 --pmc FETCH_SIZE --kernel-trace -d <fetch> -o run -- python3 <repo>/bench.py --kernels-only",
+        "  rocprofv3 --pmc WRITE_SIZE --kernel-trace -d <write> -o run -- python3 <repo>/bench.py --kernels-only",
+        "  rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --kernel-trace -d <hit> -o run -- python3 <repo>/bench.py --kernels-only",
+        "  python3 bench.py --counter-summary <fetch> <write> <hit> > profiles/adjoint_traffic_512x512x64_40views.txt",
+        "FETCH_SIZE and WRITE_SIZE are scaled by (bytes a plain 256 MiB device copy moves) / (what the counter",
+        "reads for that copy); L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).  Values are means per dispatch.",
+        "",
+        "  %-36s %14s %14s %10s %10s" % ("kernel", "FETCH_SIZE KiB", "WRITE_SIZE KiB", "HBM GB", "L2 hit"),
+    ] + rows + [
+        "",
+        "  copy calibration: FETCH x %.3f, WRITE x %.3f" % (cf, cw),
+        "",
+        "Machine-readable (bench.py reports hbm_bytes_per_launch as roofline.traffic and the L2 hit rate",
+        "while the digest of %s still matches):" % ", ".join(TRAFFIC_SOURCES),
+        "kernel: k_adj_profiles + k_adj_gather_staged",
+        "hbm_bytes_per_launch: %.0f" % (pt_gb * 1e9),
+        "l2_hit_rate: %.4f" % (pt_hit / (pt_hit + pt_miss)),
+        "forward_hbm_bytes_per_launch: %.0f" % (got["k_forward_runs"][0] * 1e9),
+        "sources_sha256: %s" % sources_digest(TRAFFIC_SOURCES),
+    ]
+    print("\n".join(lines))
+
+
+def trace_summary(d, top=40):
+    """Per kernel and launch grid: calls, total / mean / min / max duration, share, VGPRs and LDS,
+    from the kernel trace in a rocprofv3 output directory (its SQLite database)."""
+    import glob
+    import re
+    import sqlite3
+    from collections import defaultdict
+
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit("no rocprofv3 database under %s" % d)
+    con = sqlite3.connect(dbs[0])
+    acc, meta = defaultdict(list), {}
+    for name, dur, vg, lds, gx, gy, gz in con.execute(
+            "select name, duration, vgpr_count, lds_size, grid_x, grid_y, grid_z from kernels"):
+        n = re.sub(r"^void ", "", name).replace("(anonymous namespace)::", "")
+        n = re.sub(r"\((float|double|int|long|unsigned|ColParams|RofControl|AdjArgs|SidArgs|SidCol|const|ZIndex|"
+                   r"ViewParams).*$", "", n)
+        n = "%s [%dx%dx%d]" % (n, gx, gy, gz)
+        acc[n].append(dur)
+        meta[n] = (vg, lds)
+    tot = sum(sum(v) for v in acc.values())
+    w = 62
+    print("%-*s %6s %9s %9s %8s %8s %6s %5s %6s" % (w, "kernel", "calls", "total ms", "mean us", "min us", "max us", "%",
+                                                 "vgpr", "lds"))
+    for n, v in sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        vg, lds = meta[n]
+        print("%-*s %6d %9.3f %9.2f %8.2f %8.2f %6.2f %5d %6d" % (w, n[:w], len(v), sum(v) / 1e6, sum(v) / len(v) / 1e3,
+                                                              min(v) / 1e3, max(v) / 1e3, 100 * sum(v) / tot, vg, lds))
+    print("all kernels: %.3f ms" % (tot / 1e6))
 
 
 def main():
@@ -162,7 +300,16 @@ def main():
     ap.add_argument("--serving", type=int, default=32, metavar="N",
                     help="requests of the serving workload to replay (256 in the full workload; 0: skip)")
     ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (for counters)")
+    ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "HIT_DIR"),
+                    help="print the traffic / L2 hit-rate record from three counter runs of --kernels-only")
+    ap.add_argument("--trace-summary", metavar="DIR", help="per-kernel table of a rocprofv3 kernel-trace run")
     args = ap.parse_args()
+    if args.counter_summary:
+        counter_summary(*args.counter_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.kernels_only:
         kernels_only()
         return
@@ -288,12 +435,13 @@ def main():
     alg_bytes = 4.0 * vv + 8.0 * g.n_views * g.nu * g.nv
     # the dominant operator: P^T (two launches, z profiles then the gather) or P (one launch)
     if ta >= tp:
-        dom, t_dom, traffic = "P^T: k_adj_profiles + k_adj_gather_staged", ta, measured_traffic()
+        dom, t_dom = "P^T: k_adj_profiles + k_adj_gather_staged", ta
+        traffic, l2_hit = measured_traffic()
     else:
-        dom, t_dom, traffic = "P: k_forward", tp, None
+        dom, t_dom, traffic, l2_hit = "P: k_forward_runs", tp, None, None
     achieved = alg_bytes / t_dom / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "l2_hit_rate": l2_hit, "kernel": dom,
                 "kernel_ms": t_dom * 1e3, "bytes_per_launch": alg_bytes}
 
     res = {
