@@ -69,7 +69,7 @@ std::string geom_key(const cbct_geometry_desc &g, const std::vector<double> &ang
 // reconstruction workspace bytes for a geometry, as cbct_reconstruct_workspace_size computes it
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<int> &iters) {
+size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<int> &iters, int projector) {
     const size_t nvox = (size_t)g.nx * g.ny * g.nz, nray = (size_t)g.n_views * g.nu * g.nv;
     size_t b = 5 * align256(4 * nvox) + align256(4 * std::max(nray, nvox));
     for (int l = 1; l < levels; l++) b += align256(4 * (nray >> (2 * l)));
@@ -86,7 +86,10 @@ size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<in
         const double diag = std::sqrt(std::pow((nx + 2) * hx, 2) + std::pow((ny + 2) * hy, 2));
         const size_t zf = (size_t)g.n_views * nu * (((size_t)std::ceil(diag / dtau) + 4) * (size_t)nz + 32) + 64 +
                           (size_t)cbct_adj_vsplit(nx, ny, nz, g.n_views) * nx * ny * nz;
-        zmax = std::max(zmax, zf);
+        // the Siddon pair's profile tables instead: (nx + ny + 3) pieces x nz cells per line
+        const size_t lines = (size_t)g.n_views * nu;
+        const size_t zs = align256(lines * (size_t)(nx + ny + 3) * nz * 4) / 4 + lines * 4;
+        zmax = std::max(zmax, projector == 1 ? zs : zf);
     }
     b += align256(4 * zmax);
     int slots = 0;
@@ -199,6 +202,9 @@ void run_request(cbct_server *s, Request *r, hipStream_t stream) {
     size_t ws_need = 0;
     r->p.iters = r->iters.data();
     st = cbct_reconstruct_workspace_size(plan, &r->p, &ws_need);
+    if (!st && ws_need > r->ws_bytes)  // admission counted r->ws_bytes against the budget
+        st = cbct_set_error(CBCT_ERR_INTERNAL, "server: workspace %zu bytes exceeds its admission estimate %zu",
+                             ws_need, r->ws_bytes);
     Block ws{}, yb{};
     if (!st) {
         ws = block_get(s, ws_need);
@@ -301,7 +307,7 @@ cbct_status submit(cbct_server *s, const cbct_geometry_desc *g, const cbct_solve
     r->y_on_host = y_on_host;
     r->d_out = d_out;
     r->sim_seconds = sim_seconds;
-    r->ws_bytes = estimate_ws(*g, p->levels, r->iters);
+    r->ws_bytes = estimate_ws(*g, p->levels, r->iters, p->projector);
     const size_t tables = (size_t)p->levels * g->n_views * (g->nu * sizeof(ColParams) + sizeof(ViewParams));
     r->bytes = r->ws_bytes + tables + (y_on_host ? sizeof(float) * (size_t)g->n_views * g->nu * g->nv : 0);
     if (r->bytes > s->budget)

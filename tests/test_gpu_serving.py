@@ -52,6 +52,27 @@ def test_mixed_requests_equal_solo_results():
     srv.close()
 
 
+def test_mixed_operator_choices_equal_solo_results():
+    """Requests with the Siddon pair, Siddon P + Eq. 6, and the trilinear pair in one mix: each
+    result equals its solo solve bitwise, and the admission estimate covers the Siddon tables."""
+    from paper_1001_0599_amd.ops import Plan
+    from paper_1001_0599_amd.serving import Server
+    announce("serving: 6 requests, three operator choices, 3 slots")
+    reqs = _requests()
+    kws = [dict(projector=1), dict(projector=1, step1_eq6=1), dict()] * 2
+    solo = [Plan(g).reconstruct(y, lam=0.05, iters=[6], **kw) for (g, y), kw in zip(reqs, kws)]
+    torch.cuda.synchronize()
+    srv = Server(budget_bytes=4e9, max_slots=3)
+    outs = [torch.empty(g.vol_shape, device="cuda") for g, _ in reqs]
+    tickets = [srv.submit(g, y, o, lam=0.05, iters=(6,), **kw) for (g, y), o, kw in zip(reqs, outs, kws)]
+    srv.wait_all()
+    for t, o, s in zip(tickets, outs, solo):
+        done, status, _ = srv.poll(t)
+        assert done and status == 0, srv.poll(t)
+        assert torch.equal(o, s)
+    srv.close()
+
+
 def test_budget_serialises_when_tight():
     from paper_1001_0599_amd.serving import Server
     reqs = _requests()[:3]

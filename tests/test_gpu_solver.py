@@ -169,6 +169,19 @@ def test_reconstruct_siddon_two_levels():
     assert e < 1e-3, (e, replayed)
 
 
+def test_reconstruct_siddon_ragged():
+    """Ragged sizes (no dimension a multiple of a tile, odd detector rows, 7 views) with the
+    Siddon pair, and with Siddon P + Eq. 6."""
+    g = dataclasses.replace(G1, nx=23, ny=19, nz=13, nu=37, nv=29, n_views=7)
+    ph = S.make_phantom(g, 51)
+    Y = S.poisson_log(S.analytic_projections(g, ph), 1e5, 52)
+    for kw in (dict(projector=1), dict(projector=1, step1_eq6=True)):
+        announce("reconstruct 23x19x13, 7 views, 10 iterations, %s" % kw)
+        e, replayed, res, st = _compare_solve(g, Y, 0.05, [10], 1, **kw)
+        assert e < 1e-3, (kw, e, replayed)
+        assert rel_l2(st["energy"], res.energy) < 1e-4, kw
+
+
 def test_reconstruct_siddon_tall_volume():
     """A tall thin volume (352 z cells): too many for the run-summing Siddon projector's
     tables, so the residual takes the per-ray walk and its separate residual pass.  Four views
