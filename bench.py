@@ -129,7 +129,7 @@ def serving_run(n_requests):
 
 def kernels_only():
     """One launch each of a plain 256 MB copy and the hot kernels at the 512x512x64 / 40-view size:
-    P (k_forward_runs), P^T (k_adj_profiles + k_adj_gather_staged), the Eq. 6 backprojector, the
+    P (k_forward_runs), P^T (k_adj_profiles, k_adj_gather_staged, k_adj_combine), the Eq. 6 backprojector, the
     Siddon pair, and one Step 2 solve (k_tv_grad, k_tv_trial, ...); the driver for hardware-counter
     runs, whose records `--counter-summary` turns into the traffic and L2 hit-rate table."""
     import torch
@@ -170,6 +170,7 @@ COUNTER_KERNELS = [  # (label, kernel-name prefix) in the order of the table
     ("P: k_forward_runs", "k_forward_runs"),
     ("P^T pass 1: k_adj_profiles", "k_adj_profiles"),
     ("P^T pass 2: k_adj_gather_staged", "k_adj_gather_staged"),
+    ("P^T view-group sum: k_adj_combine", "k_adj_combine"),
     ("Eq. 6: k_backproject_eq6", "k_backproject_eq6"),
     ("P_s: k_siddon_forward_runs", "k_siddon_forward_runs"),
     ("P_s^T pass 1: k_sid_profiles", "k_sid_profiles"),
@@ -229,9 +230,10 @@ def counter_summary(fetch_dir, write_dir, hit_dir):
         hit = hi / (hi + mi) if hi is not None and mi is not None and hi + mi > 0 else float("nan")
         got[pre] = (gb, hi or 0.0, mi or 0.0)
         rows.append("  %-36s %14.1f %14.1f %10.3f %9.1f%%" % (label, fs, ws, gb, 100 * hit))
-    pt_gb = got["k_adj_profiles"][0] + got["k_adj_gather_staged"][0]
-    pt_hit = sum(got[k][1] for k in ("k_adj_profiles", "k_adj_gather_staged"))
-    pt_miss = sum(got[k][2] for k in ("k_adj_profiles", "k_adj_gather_staged"))
+    pt_kernels = [k for k in ("k_adj_profiles", "k_adj_gather_staged", "k_adj_combine") if k in got]
+    pt_gb = sum(got[k][0] for k in pt_kernels)
+    pt_hit = sum(got[k][1] for k in pt_kernels)
+    pt_miss = sum(got[k][2] for k in pt_kernels)
     lines = [
         "HBM traffic and L2 hit rate per launch from hardware counters, 512x512x64 voxels, 40 views,",
         "512x384 detector (MI355X, gfx950).  Three rocprofv3 runs of the same program, from the repository root:",
@@ -250,7 +252,7 @@ def counter_summary(fetch_dir, write_dir, hit_dir):
         "",
         "Machine-readable (bench.py reports hbm_bytes_per_launch as roofline.traffic and the L2 hit rate",
         "while the digest of %s still matches):" % ", ".join(TRAFFIC_SOURCES),
-        "kernel: k_adj_profiles + k_adj_gather_staged",
+        "kernel: " + " + ".join(pt_kernels),
         "hbm_bytes_per_launch: %.0f" % (pt_gb * 1e9),
         "l2_hit_rate: %.4f" % (pt_hit / (pt_hit + pt_miss)),
         "forward_hbm_bytes_per_launch: %.0f" % (got["k_forward_runs"][0] * 1e9),
@@ -435,7 +437,7 @@ def main():
     alg_bytes = 4.0 * vv + 8.0 * g.n_views * g.nu * g.nv
     # the dominant operator: P^T (two launches, z profiles then the gather) or P (one launch)
     if ta >= tp:
-        dom, t_dom = "P^T: k_adj_profiles + k_adj_gather_staged", ta
+        dom, t_dom = "P^T: k_adj_profiles + k_adj_gather_staged + k_adj_combine", ta
         traffic, l2_hit = measured_traffic()
     else:
         dom, t_dom, traffic, l2_hit = "P: k_forward_runs", tp, None, None

@@ -45,13 +45,15 @@ def test_counter_summary(tmp_path, capsys):
     fetch = {n: [copy_read / kib / 2] for n in names}  # FETCH reads half of what moves (factor 2)
     fetch["k_adj_profiles<true>"] = fetch.pop("k_adj_profiles")
     fetch["k_adj_profiles<true>"] = [1000.0, 3000.0]  # mean 2000 KiB -> 2 x 2000 KiB
+    fetch["k_adj_combine"] = [100.0]
     write = {n: [0.0] for n in fetch}
+    write["k_adj_combine"] = [50.0]
     write["k_adj_gather_staged<32, 288>"] = write.pop("k_adj_gather_staged")
     write["k_adj_gather_staged<32, 288>"] = [4096.0]
     fetch["k_adj_gather_staged<32, 288>"] = fetch.pop("k_adj_gather_staged")
     hits = {n: [30.0] for n in fetch}
     miss = {n: [10.0] for n in fetch}
-    miss["k_adj_profiles<true>"] = [90.0]  # profiles 30 / 120, gather 30 / 40
+    miss["k_adj_profiles<true>"] = [90.0]  # profiles 30 / 120, gather and sum 30 / 40 each
     _db(str(tmp_path / "f"), _rows("FETCH_SIZE", copy_read / kib / 2, fetch))
     _db(str(tmp_path / "w"), _rows("WRITE_SIZE", copy_read / kib, write))
     _db(str(tmp_path / "h"), _rows("TCC_HIT_sum", 1.0, hits) + _rows("TCC_MISS_sum", 1.0, miss))
@@ -61,9 +63,11 @@ def test_counter_summary(tmp_path, capsys):
     kv = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     # P^T = profiles (2 x 2000 KiB fetched) + gather (2 x copy_read/2 fetched + 4096 KiB written)
-    want = 2 * 2000 * kib + copy_read + 4096 * kib
+    # + view-group sum (2 x 100 KiB fetched + 50 KiB written)
+    want = 2 * 2000 * kib + copy_read + 4096 * kib + 2 * 100 * kib + 50 * kib
     assert float(kv["hbm_bytes_per_launch"]) == pytest.approx(want, rel=1e-9)
-    assert float(kv["l2_hit_rate"]) == pytest.approx(60.0 / 160.0)
+    assert float(kv["l2_hit_rate"]) == pytest.approx(90.0 / 200.0)
+    assert kv["kernel"] == "k_adj_profiles + k_adj_gather_staged + k_adj_combine"
     assert float(kv["forward_hbm_bytes_per_launch"]) == pytest.approx(copy_read, rel=1e-9)
     assert kv["sources_sha256"] == bench.sources_digest(bench.TRAFFIC_SOURCES)
 
