@@ -287,10 +287,12 @@ __global__ void __launch_bounds__(256)
 // samples of each inside the box (+ one voxel), stages those profile rows in LDS with coalesced
 // loads (8 lanes per row), and every voxel column then gathers its hits from LDS.  Each profile
 // line is read from L2 once per tile and view instead of once per voxel that uses it.
-// Tiles of 32 z cells stage 288 rows per batch (3 work-groups per CU): on MI355X at 512x512x64 /
-// 40 views this was the fastest of 160 to 448 rows, and faster than tiles of 64 cells (whole
-// profile rows, 2 work-groups per CU: 2.16 against 1.99 ms per P^T).
-constexpr int GS_ROWS32 = 288;
+// Tiles of 32 z cells stage 320 rows per batch (52 KB of LDS: 3 work-groups per CU): on MI355X at
+// 512x512x64 / 40 views in two view groups this measured 1.69-1.71 ms per P^T against 1.73-1.75
+// for 288 rows and 1.80 for 224 or 256 (one view group: 288 was the fastest of 160 to 448), and
+// tiles of 32 cells beat tiles of 64 (whole profile rows, 2 work-groups per CU: 2.16 against 1.99
+// ms per P^T in one group).
+constexpr int GS_ROWS32 = 320;
 constexpr int GS_CC = 64;  // detector columns per column chunk (one wave lists them)
 
 struct GsCol {
