@@ -165,7 +165,7 @@ struct RofControl {
     int m;           // its backtracking exponent
     int accepted;    // 1: step accepted, -1: no admissible step, 0: search continues at next_m0
     int next_m0;
-    int pad;
+    int pad;         // in the host-mapped copy: the decision call's sequence number, written last
 };
 
 int cbct_reduce_blocks(const Level &L);
@@ -178,7 +178,7 @@ cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, con
                                  double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s);
 cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
                                    double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
-                                   RofControl *mirror, hipStream_t s);
+                                   RofControl *mirror, int seq, hipStream_t s);
 cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ctl, long n, hipStream_t s);
 cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s);
 

@@ -10,6 +10,7 @@
 // the 64-byte decision record once per ROF iteration to steer the loop.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -45,6 +46,30 @@ MappedSlot mapped_ctl() {
         }
     }
     return slot;
+}
+
+// sequence numbers of the decision records of this host thread (never 0, the value the kernel
+// writes into the record before its fields)
+int next_seq() {
+    thread_local int n = 0;
+    n = (n == 0x7fffffff) ? 1 : n + 1;
+    return n;
+}
+
+// wait until the host-mapped record carries `seq`: true when seen within the polling window
+// (about 20 ms), false otherwise (the caller then synchronises the stream, after which the
+// record is complete)
+bool poll_seq(const RofControl *rec, int seq) {
+    const volatile int *p = &rec->pad;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0;; spin++) {
+        if (*p == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return true;
+        }
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20))
+            return false;
+    }
 }
 
 std::mutex g_schur_mu;
@@ -213,12 +238,16 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
                                            s)))
                 return st;
             const MappedSlot ms = mapped_ctl();
+            const int seq = next_seq();
             if ((st = cbct_launch_rof_decide(b.sums, m0, M, forced >= 0 ? forced : -1, L.nvox(), pr->lambda, t,
-                                             pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, ms.dev, s)))
+                                             pr->armijo_c, pr->backtrack, pr->rof_max_backtrack, b.ctl, ms.dev, seq,
+                                             s)))
                 return st;
             if (ms.host) {
-                CBCT_HIP(hipStreamSynchronize(s));
-                std::memcpy(&c, ms.host, sizeof(c));  // the kernel's writes are visible after the sync
+                // the record is complete once its sequence number shows: poll it for a while (the
+                // kernel writes it before the stream reports completion), then block on the stream
+                if (!poll_seq(ms.host, seq)) CBCT_HIP(hipStreamSynchronize(s));
+                std::memcpy(&c, ms.host, sizeof(c));
             } else {
                 CBCT_HIP(hipMemcpyAsync(&c, b.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
                 CBCT_HIP(hipStreamSynchronize(s));

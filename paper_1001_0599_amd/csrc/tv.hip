@@ -251,11 +251,12 @@ __global__ void k_axpy_step(float *__restrict__ u, const float *__restrict__ d, 
 
 // Armijo decision for one ROF iteration from the reduced sums.
 // sums: [0..2] = {sum phi(u), sum (u-g)^2, sum d^2}, [3 + 2m + {0,1}] = trial sums for m - m0.
-// The record goes to ctl (read by the update kernel) and, when given, to a host-mapped mirror that
-// the host reads after synchronising the stream (no copy command).
+// The record goes to ctl (read by the update kernel) and, when given, to a host-mapped mirror
+// (no copy command): its fields first, then, after a system-scope fence, the call's sequence
+// number in `pad`, so that a host that sees the number also sees the fields.
 __global__ void k_rof_decide(const double *__restrict__ sums, int M, int m0, int forced_m, double inv_n, double lambda,
                              double t, double c_armijo, double alpha, int max_bt, RofControl *__restrict__ ctl,
-                             RofControl *__restrict__ mirror) {
+                             RofControl *__restrict__ mirror, int seq) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     RofControl r{};
     r.e0 = lambda * sums[0] * inv_n + sums[1] * inv_n / (2.0 * t);
@@ -284,7 +285,12 @@ __global__ void k_rof_decide(const double *__restrict__ sums, int M, int m0, int
         else r.accepted = -1;
     }
     *ctl = r;
-    if (mirror) *mirror = r;
+    if (mirror) {
+        r.pad = 0;
+        *mirror = r;
+        __threadfence_system();
+        *reinterpret_cast<volatile int *>(&mirror->pad) = seq;
+    }
 }
 
 }  // namespace
@@ -353,9 +359,9 @@ cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, con
 
 cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced_m, long nvox, double lambda,
                                    double t, double c_armijo, double alpha, int max_bt, RofControl *ctl,
-                                   RofControl *mirror, hipStream_t s) {
+                                   RofControl *mirror, int seq, hipStream_t s) {
     hipLaunchKernelGGL(k_rof_decide, dim3(1), dim3(64), 0, s, sums, M, m0, forced_m, 1.0 / (double)nvox, lambda, t,
-                       c_armijo, alpha, max_bt, ctl, mirror);
+                       c_armijo, alpha, max_bt, ctl, mirror, seq);
     LAUNCH_CHECK("k_rof_decide");
     return CBCT_OK;
 }
