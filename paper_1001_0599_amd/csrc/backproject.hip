@@ -478,14 +478,17 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// out = sum of the view groups' partial volumes (in group order), or fbase - kappa * that sum
+// out = sum of the view groups' partial volumes (in group order), or fbase - kappa * that sum;
+// also into out2 when given (the solver's ROF start u = g, saving a copy pass)
 __global__ void __launch_bounds__(256) k_adj_combine(const float *__restrict__ part, int vgroups, long n,
                                                      const float *__restrict__ fbase, float kappa,
-                                                     float *__restrict__ out) {
+                                                     float *__restrict__ out, float *__restrict__ out2) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         float s = part[i];
         for (int g = 1; g < vgroups; g++) s += part[g * n + i];
-        out[i] = fbase ? fmaf(-kappa, s, fbase[i]) : s;
+        const float v = fbase ? fmaf(-kappa, s, fbase[i]) : s;
+        out[i] = v;
+        if (out2) out2[i] = v;
     }
 }
 
@@ -511,7 +514,15 @@ cbct_status launch_gather(const Level &L, const float *Z, const float *fbase, fl
 }  // namespace
 
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
-                                float *Zws, hipStream_t s, bool preweighted) {
+                                float *Zws, hipStream_t s, bool preweighted, float *out2) {
+    // out2: the view-group sum writes it too; the other paths copy out into it
+    const auto copy_out2 = [&]() -> cbct_status {
+        if (out2) {
+            hipError_t e = hipMemcpyAsync(out2, out, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return cbct_hip_error(e, "adjoint: copy of the result");
+        }
+        return CBCT_OK;
+    };
     size_t lds = sizeof(double2) * (L.nv + 1 + L.zk_max);
     const bool gb_lds = lds <= 64 * 1024;
     if (!gb_lds) lds = sizeof(double2) * (L.nv + 1);
@@ -535,10 +546,11 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
         if (vg > 1) {
             const long n = L.nvox();
             const int nb = (int)std::min<long>((n + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out);
+            hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out, out2);
             LAUNCH_CHECK("k_adj_combine");
+            return CBCT_OK;
         }
-        return CBCT_OK;
+        return copy_out2();
     }
     // other depths: per-lane gather, z cells per thread up to 64 (the window and weight work per
     // voxel column and view is shared by all its cells)
@@ -548,10 +560,12 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
     else if (nz % 16 == 0) tz = 16;
     else if (nz % 8 == 0) tz = 8;
     else tz = nz > 32 ? 64 : nz > 16 ? 32 : nz > 8 ? 16 : 8;  // partial last tile, scalar loads
+    cbct_status st;
     switch (tz) {
-        case 64: return launch_gather<64>(L, Zws, fbase, kappa, out, s);
-        case 32: return launch_gather<32>(L, Zws, fbase, kappa, out, s);
-        case 16: return launch_gather<16>(L, Zws, fbase, kappa, out, s);
-        default: return launch_gather<8>(L, Zws, fbase, kappa, out, s);
+        case 64: st = launch_gather<64>(L, Zws, fbase, kappa, out, s); break;
+        case 32: st = launch_gather<32>(L, Zws, fbase, kappa, out, s); break;
+        case 16: st = launch_gather<16>(L, Zws, fbase, kappa, out, s); break;
+        default: st = launch_gather<8>(L, Zws, fbase, kappa, out, s); break;
     }
+    return st ? st : copy_out2();
 }

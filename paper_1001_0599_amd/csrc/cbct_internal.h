@@ -131,9 +131,11 @@ cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float 
 // out = B proj (f_base == NULL) or f_base - kappa B proj, B the Eq. 6 backprojector.
 cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const float *f_base, float kappa,
                                         float *out, hipStream_t s);
-// out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats.
+// out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats; out2
+// (optional) receives the same volume.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
-                                float *out, float *Zws, hipStream_t s, bool preweighted = false);
+                                float *out, float *Zws, hipStream_t s, bool preweighted = false,
+                                float *out2 = nullptr);
 // Siddon pair: out = P_s vol_t (vol_t in the column-major layout), or with y_sub the residual
 // out = P_s vol_t - y_sub and partials[view * nu + i] = sum of its squares; out = P_s^T proj, or
 // f_base - kappa P_s^T proj.

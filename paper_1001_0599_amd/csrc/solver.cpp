@@ -207,11 +207,12 @@ struct TraceSink {
     }
 };
 
-// Step 2: u = ROF(g) from u = g.  `replay_pos` walks params.replay.
+// Step 2: u = ROF(g) from u = g (u_ready: Step 1 has written u already).  `replay_pos` walks
+// params.replay.
 cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, const Bufs &b, hipStream_t s,
-                     TraceSink &sink, int level, int outer, int *replay_pos) {
+                     TraceSink &sink, int level, int outer, int *replay_pos, bool u_ready = false) {
     cbct_status st;
-    CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+    if (!u_ready) CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < pr->rof_max_iter; it++) {
         int forced = -2;  // free running
         if (pr->replay && *replay_pos < pr->replay_len) forced = pr->replay[(*replay_pos)++];
@@ -390,10 +391,10 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             else if (proj == 1)
                 st = cbct_launch_adjoint_siddon(L, b.r, b.f, kappa, b.g, b.z, s);
             else
-                st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true);
+                st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true, b.u);  // u = g as well
             if (st) return st;
             // Step 2
-            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos))) return st;
+            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, !eq6 && proj != 1))) return st;
             // Step 3
             if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s))) return st;
         }
