@@ -188,6 +188,9 @@ cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *
 cbct_status cbct_launch_prolong(const Level &coarse, const float *c, float *f, hipStream_t s);
 cbct_status cbct_launch_restrict(const Level &coarse, const float *f, float *c, hipStream_t s);
 cbct_status cbct_launch_bin(const Level &fine0, int factor, const float *y0, float *yl, hipStream_t s);
-cbct_status cbct_launch_clamp_columns(const Level &L, const float *u, float *f, float *f_t, hipStream_t s);
+// f = max(v, 0) and its column-major copy f_t, v = u, or u - s d when d is given and the decision
+// record ctl accepted a step of size s (a ROF update left pending by the loop).
+cbct_status cbct_launch_clamp_columns(const Level &L, const float *u, float *f, float *f_t, hipStream_t s,
+                                      const float *d = nullptr, const RofControl *ctl = nullptr);
 cbct_status cbct_launch_fill(float *x, long n, float v, hipStream_t s);
 cbct_status cbct_launch_max(const float *x, long n, double *partials, double *out, hipStream_t s);

@@ -95,9 +95,13 @@ __global__ void __launch_bounds__(256) k_bin(const float *__restrict__ y0, float
 }
 
 // Step 3 (f = max(u, 0)) fused with the copy of f into the projector's column-major layout
-__global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__ u, float *__restrict__ f,
+__global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__ u, const float *__restrict__ d,
+                                                       const RofControl *__restrict__ ctl, float *__restrict__ f,
                                                        float *__restrict__ f_t, int nx, int ny, int nz) {
     __shared__ float tile[32][33];
+    // a pending accepted ROF step u - s d is applied here (the same product as the update kernel's)
+    const bool step = d && ctl->accepted == 1;
+    const float st = step ? (float)ctl->s : 0.0f;
     const int b = blockIdx.z;
     const int a0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -105,7 +109,7 @@ __global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__
         const int c = c0 + r, a = a0 + tx;
         if (c < nz && a < nx) {
             const long p = ((long)c * ny + b) * nx + a;
-            const float v = fmaxf(u[p], 0.0f);
+            const float v = fmaxf(step ? fmaf(-st, d[p], u[p]) : u[p], 0.0f);
             f[p] = v;
             tile[r][tx] = v;
         }
@@ -180,9 +184,10 @@ cbct_status cbct_launch_bin(const Level &fine0, int factor, const float *y0, flo
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_clamp_columns(const Level &L, const float *u, float *f, float *f_t, hipStream_t s) {
+cbct_status cbct_launch_clamp_columns(const Level &L, const float *u, float *f, float *f_t, hipStream_t s,
+                                      const float *d, const RofControl *ctl) {
     dim3 grid((L.nx + 31) / 32, (L.nz + 31) / 32, L.ny);
-    hipLaunchKernelGGL(k_clamp_columns, grid, dim3(32, 8), 0, s, u, f, f_t, L.nx, L.ny, L.nz);
+    hipLaunchKernelGGL(k_clamp_columns, grid, dim3(32, 8), 0, s, u, d, ctl, f, f_t, L.nx, L.ny, L.nz);
     LAUNCH_CHECK("k_clamp_columns");
     return CBCT_OK;
 }

@@ -208,9 +208,12 @@ struct TraceSink {
 };
 
 // Step 2: u = ROF(g) from u = g (u_ready: Step 1 has written u already).  `replay_pos` walks
-// params.replay.
+// params.replay.  With `pending`, an accepted step that ends the loop is not applied to u; the
+// caller's Step 3 applies it (*pending = true, the step in b.ctl).
 cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, const Bufs &b, hipStream_t s,
-                     TraceSink &sink, int level, int outer, int *replay_pos, bool u_ready = false) {
+                     TraceSink &sink, int level, int outer, int *replay_pos, bool u_ready = false,
+                     bool *pending = nullptr) {
+    if (pending) *pending = false;
     cbct_status st;
     if (!u_ready) CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < pr->rof_max_iter; it++) {
@@ -263,8 +266,14 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
             return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (level %d, outer %d)", level, outer);
         sink.push(level, outer, it, c.accepted == 1 ? c.m : -1, c);
         if (c.accepted != 1) break;  // Eq. 5 held for no step: keep u
+        const bool stop = c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol ||
+                          it + 1 == pr->rof_max_iter;
+        if (stop && pending) {
+            *pending = true;
+            break;
+        }
         if ((st = cbct_launch_axpy_step(b.u, b.d, b.ctl, L.nvox(), s))) return st;
-        if (c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol) break;
+        if (stop) break;
     }
     return CBCT_OK;
 }
@@ -394,9 +403,12 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
                 st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true, b.u);  // u = g as well
             if (st) return st;
             // Step 2
-            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, !eq6 && proj != 1))) return st;
-            // Step 3
-            if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s))) return st;
+            bool pending = false;
+            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, !eq6 && proj != 1, &pending))) return st;
+            // Step 3 (with the last ROF update when it is pending)
+            if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s, pending ? b.d : nullptr,
+                                                pending ? b.ctl : nullptr)))
+                return st;
         }
     }
     CBCT_HIP(hipMemcpyAsync(d_out, b.f, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
