@@ -208,8 +208,9 @@ cbct_status cbct_reconstruct_workspace_size(const cbct_plan *plan, const cbct_so
 /* Full reconstruction.  d_y: level-0 projections [n_views][nv][nu]; d_init: NULL or a level-0
  * start volume; d_out: level-0 result [nz][ny][nx]; d_ws: >= cbct_reconstruct_workspace_size
  * bytes, 256-byte aligned, not shared with a concurrent call.  The call steers the ROF loop
- * from the host: it synchronises `stream` once per ROF iteration to read the device-side Armijo
- * decision (64 bytes), and returns when d_out is final.  The plan's Schur-step cache is the
+ * from the host: once per ROF iteration it waits for the device-side Armijo decision (64 bytes,
+ * written into host-mapped memory and polled, or read after synchronising `stream` when polling
+ * is unavailable or times out), and it returns when d_out is final.  The plan's Schur-step cache is the
  * only plan state it writes (guarded by a lock).  INVALID_ARG for bad params or workspace;
  * NONFINITE when an energy or the Schur bound is not finite. */
 cbct_status cbct_reconstruct(cbct_plan *plan, const cbct_solve_params *params, const float *d_y,
