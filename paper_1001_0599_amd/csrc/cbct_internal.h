@@ -128,9 +128,10 @@ cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_
 // and partials[view * nu + i] = sum (P f - y_sub)^2.
 cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float *y_sub, float *out,
                                 double *partials, hipStream_t s, bool weight_residual = true);
-// out = B proj (f_base == NULL) or f_base - kappa B proj, B the Eq. 6 backprojector.
+// out = B proj (f_base == NULL) or f_base - kappa B proj, B the Eq. 6 backprojector; out2
+// (optional) receives the same volume.
 cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const float *f_base, float kappa,
-                                        float *out, hipStream_t s);
+                                        float *out, hipStream_t s, float *out2 = nullptr);
 // out = P^T proj (f_base == NULL) or f_base - kappa P^T proj; Zws holds L.z_floats floats; out2
 // (optional) receives the same volume.
 cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *f_base, float kappa,
@@ -143,7 +144,7 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, const
                                        double *partials, hipStream_t s);
 // P_s^T through per-piece z profiles in ws (cbct_adjoint_siddon_ws_bytes), or the per-cell gather
 cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const float *f_base, float kappa, float *out,
-                                       void *ws, hipStream_t s);
+                                       void *ws, hipStream_t s, float *out2 = nullptr);
 size_t cbct_adjoint_siddon_ws_bytes(const Level &L);
 
 // ---- solver pieces --------------------------------------------------------------------------

@@ -22,7 +22,8 @@ constexpr int EQ6_ZC = 16;  // z cells per thread: the view's u-side terms are s
 
 __global__ void __launch_bounds__(256)
     k_backproject_eq6(const float *__restrict__ T, const ViewParams *__restrict__ views, AdjArgs A,
-                      const float *__restrict__ fbase, float kappa, float *__restrict__ out) {
+                      const float *__restrict__ fbase, float kappa, float *__restrict__ out,
+                      float *__restrict__ out2) {
     const long ncol = (long)A.nx * A.ny;
     const long tidg = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int nzc = (A.nz + EQ6_ZC - 1) / EQ6_ZC;
@@ -88,7 +89,9 @@ __global__ void __launch_bounds__(256)
         if (c < A.nz) {
             const long idx = ((long)c * A.ny + b) * A.nx + a;
             const float v = acc[q] * scale;
-            out[idx] = fbase ? fmaf(-kappa, v, fbase[idx]) : v;
+            const float o = fbase ? fmaf(-kappa, v, fbase[idx]) : v;
+            out[idx] = o;
+            if (out2) out2[idx] = o;
         }
     }
 }
@@ -96,10 +99,10 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 cbct_status cbct_launch_backproject_eq6(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
-                                        hipStream_t s) {
+                                        hipStream_t s, float *out2) {
     const long n = (long)L.nx * L.ny * ((L.nz + EQ6_ZC - 1) / EQ6_ZC);
     hipLaunchKernelGGL(k_backproject_eq6, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, proj, L.d_views, L.adj,
-                       fbase, kappa, out);
+                       fbase, kappa, out, out2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_backproject_eq6 launch");
     return CBCT_OK;

@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward(const float *__restrict_
 __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__ proj, const SidCol *__restrict__ cols,
                                                        const ViewParams *__restrict__ views, SidArgs A,
                                                        const float *__restrict__ fbase, float kappa,
-                                                       float *__restrict__ out) {
+                                                       float *__restrict__ out, float *__restrict__ out2) {
     const int ntx = (A.nx + 15) / 16, nzc = (A.nz + SID_TZ - 1) / SID_TZ;
     int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
     const int zc = w % nzc;
@@ -210,7 +210,9 @@ __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__
     for (int k = 0; k < SID_TZ; k++)
         if (c0 + k < A.nz) {
             const long o = (c0 + k) * plane + (long)b * A.nx + a;
-            out[o] = fbase ? fmaf(-kappa, acc[k], fbase[o]) : acc[k];
+            const float v = fbase ? fmaf(-kappa, acc[k], fbase[o]) : acc[k];
+            out[o] = v;
+            if (out2) out2[o] = v;
         }
 }
 
@@ -624,7 +626,7 @@ __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restri
                                                            const SidCol *__restrict__ cols,
                                                            const ViewParams *__restrict__ views, SidArgs A, int kmax,
                                                            const float *__restrict__ fbase, float kappa,
-                                                           float *__restrict__ out) {
+                                                           float *__restrict__ out, float *__restrict__ out2) {
     const int ntx = (A.nx + 7) / 8;
     const int w = cbct_xcd_remap(blockIdx.x, gridDim.x);
     const int g = threadIdx.x & 3, q = threadIdx.x >> 2;
@@ -682,7 +684,9 @@ __global__ void __launch_bounds__(256) k_sid_gather_pieces(const float *__restri
     for (int u = 0; u < SGC; u++)
         if (c0 + u < nz) {
             const long o = (c0 + u) * plane + (long)b * A.nx + a;
-            out[o] = fbase ? fmaf(-kappa, acc[u], fbase[o]) : acc[u];
+            const float v = fbase ? fmaf(-kappa, acc[u], fbase[o]) : acc[u];
+            out[o] = v;
+            if (out2) out2[o] = v;
         }
 }
 
@@ -778,7 +782,7 @@ size_t cbct_adjoint_siddon_ws_bytes(const Level &L) {
 }
 
 cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
-                                       void *ws, hipStream_t s) {
+                                       void *ws, hipStream_t s, float *out2) {
     const int kmax = L.nx + L.ny + 3;
     const size_t lds = (size_t)(3 * L.nv + 1) * 4 + (size_t)(kmax + 1) * 4 + (size_t)4 * 64 * (16 + 1) * 4;
     if (lds <= 64 * 1024) {
@@ -791,7 +795,7 @@ cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const 
         if (e != hipSuccess) return cbct_hip_error(e, "k_sid_profiles launch");
         const dim3 grid((unsigned)(((L.nx + 7) / 8) * ((L.ny + 7) / 8)), (unsigned)((L.nz + 4 * SGC - 1) / (4 * SGC)));
         hipLaunchKernelGGL(k_sid_gather_pieces, grid, dim3(256), 0, s, Z, rec, L.d_sid, L.d_views, sid_args(L), kmax,
-                           fbase, kappa, out);
+                           fbase, kappa, out, out2);
         e = hipGetLastError();
         if (e != hipSuccess) return cbct_hip_error(e, "k_sid_gather_pieces launch");
         return CBCT_OK;
@@ -799,7 +803,7 @@ cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const 
     const long blocks = (long)((L.nx + 15) / 16) * ((L.ny + 15) / 16) * ((L.nz + SID_TZ - 1) / SID_TZ);
     if (blocks > 0x7fffffffL) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: grid too large");
     hipLaunchKernelGGL(k_siddon_gather, dim3((unsigned)blocks), dim3(256), 0, s, proj, L.d_sid, L.d_views, sid_args(L),
-                       fbase, kappa, out);
+                       fbase, kappa, out, out2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cbct_hip_error(e, "k_siddon_gather launch");
     return CBCT_OK;

@@ -395,16 +395,17 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             }
             if (last) break;
             // Step 1: g = f - kappa P^T r, or with the Eq. 6 backprojector in place of P^T
+            // (each writes the ROF start u = g as well)
             if (eq6)
-                st = cbct_launch_backproject_eq6(L, b.r, b.f, kappa, b.g, s);
+                st = cbct_launch_backproject_eq6(L, b.r, b.f, kappa, b.g, s, b.u);
             else if (proj == 1)
-                st = cbct_launch_adjoint_siddon(L, b.r, b.f, kappa, b.g, b.z, s);
+                st = cbct_launch_adjoint_siddon(L, b.r, b.f, kappa, b.g, b.z, s, b.u);
             else
-                st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true, b.u);  // u = g as well
+                st = cbct_launch_adjoint(L, b.r, b.f, kappa, b.g, b.z, s, true, b.u);
             if (st) return st;
             // Step 2
             bool pending = false;
-            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, !eq6 && proj != 1, &pending))) return st;
+            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, true, &pending))) return st;
             // Step 3 (with the last ROF update when it is pending)
             if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s, pending ? b.d : nullptr,
                                                 pending ? b.ctl : nullptr)))
