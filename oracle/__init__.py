@@ -89,6 +89,7 @@ def lib():
             L.orc_restrict.argtypes = [C.c_int, C.c_int, C.c_int, _D, _D]
             L.orc_bin_detector.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _D, _D]
             L.orc_level_geom.argtypes = [P(Geom), C.c_int, C.c_int, P(Geom)]
+            L.orc_forward_level.argtypes = [P(Geom), C.c_int, C.c_int, _D, _D]
             L.orc_reconstruct.argtypes = [P(Geom), C.c_int, P(C.c_int), P(Params), C.c_int, _D, _D, _D,
                                           P(Stats)]
             L.orc_reconstruct.restype = C.c_int
@@ -220,6 +221,19 @@ def adjoint_voxels(g, y, voxels) -> np.ndarray:
     out = np.empty(len(voxels))
     lib().orc_adjoint_voxels(h.ref(), _ptr(y), len(voxels), voxels.ctypes.data_as(_L), _ptr(out))
     return out
+
+
+def forward_level(g, level: int, f, bin_detector: bool = True) -> np.ndarray:
+    """P of multigrid level `level` of geometry g (the oracle's own level geometry: dims halved
+    per level over the same box, detector binned, sample spacing scaled) applied to f."""
+    h = _GeomHolder(g)
+    k = 1 << level
+    nz, ny, nx = g.nz // k, g.ny // k, g.nx // k
+    nv, nu = (g.nv // k, g.nu // k) if bin_detector else (g.nv, g.nu)
+    f = _f64(f).reshape(nz, ny, nx)
+    y = np.empty((g.n_views, nv, nu))
+    lib().orc_forward_level(h.ref(), int(level), int(bool(bin_detector)), _ptr(f), _ptr(y))
+    return y
 
 
 def tv_energy(g, f, eps: float = 1e-5) -> float:

@@ -560,6 +560,7 @@ void orc_adjoint_voxels(const og_geom *g, const double *y, long n, const long *v
             }
             int i0 = (int)floor(umin / g->pu + 0.5 * (g->nu - 1)) - 1, i1 = (int)ceil(umax / g->pu + 0.5 * (g->nu - 1)) + 1;
             int j0 = (int)floor(vmin / g->pv + 0.5 * (g->nv - 1)) - 1, j1 = (int)ceil(vmax / g->pv + 0.5 * (g->nv - 1)) + 1;
+            if (og_fault == 14) { i0 += 3; i1 -= 3; j0 += 3; j1 -= 3; }
             if (i0 < 0) i0 = 0;
             if (j0 < 0) j0 = 0;
             if (i1 > g->nu - 1) i1 = g->nu - 1;
@@ -706,6 +707,7 @@ static void og_rof(const og_geom *g, const double *gg, double *u, const og_param
         og_record(tc, it, ok ? m : -1, e0, enew, G);
         if (!ok) break; /* no step satisfied Eq. 5: keep u */
         memcpy(u, trial, sizeof(double) * (size_t)n);
+        if (og_fault == 15) continue;
         if (e0 == 0.0 || G == 0.0 || fabs(enew - e0) / e0 < pr->rof_tol) break;
     }
     free(d);
@@ -763,7 +765,7 @@ static double og_kappa0(const og_geom *g) { return 2.0 * (double)og_nvox(g) / (d
 static double og_schur_step(const og_geom *g, int projector) {
     double a, b;
     og_schur(g, projector, &a, &b);
-    return 1.0 / (og_kappa0(g) * a * b);
+    return 1.0 / ((og_fault == 18 ? 0.5 : 1.0) * og_kappa0(g) * a * b);
 }
 
 double orc_schur_step(const og_geom *g) { return og_schur_step(g, 0); }
@@ -782,7 +784,7 @@ void orc_fbs(const og_geom *g, const double *Y, double *f, int iters, const og_p
     double *pt = (double *)malloc(sizeof(double) * (size_t)nvox);
     double *gg = (double *)malloc(sizeof(double) * (size_t)nvox);
     double *u = (double *)malloc(sizeof(double) * (size_t)nvox);
-    double kappa = t * og_kappa0(g);
+    double kappa = t * og_kappa0(g) * (og_fault == 16 ? 0.5 : 1.0);
     og_trace_ctx tc = {st, level, 0};
     double e_prev = 0.0;
     int converged = 0;
@@ -900,9 +902,16 @@ void orc_level_geom(const og_geom *g0, int l, int bin_detector, og_geom *gl) {
     gl->hx = g0->hx * f; gl->hy = g0->hy * f; gl->hz = g0->hz * f;
     if (bin_detector) {
         gl->nu = g0->nu / f; gl->nv = g0->nv / f;
-        gl->pu = g0->pu * f; gl->pv = g0->pv * f;
+        gl->pu = g0->pu * (og_fault == 17 ? 1 : f); gl->pv = g0->pv * (og_fault == 17 ? 1 : f);
     }
-    gl->dtau = g0->dtau * f;
+    gl->dtau = g0->dtau * (og_fault == 19 ? 1 : f);
+}
+
+/* P of multigrid level l (orc_level_geom of g0) applied to a level-l volume */
+void orc_forward_level(const og_geom *g0, int l, int bin_detector, const double *f, double *y) {
+    og_geom gl;
+    orc_level_geom(g0, l, bin_detector, &gl);
+    orc_forward(&gl, f, y);
 }
 
 /* Full reconstruction: levels from the coarsest (levels-1) to the finest (0), each started

@@ -276,7 +276,7 @@ TVG = dataclasses.replace(G1, nx=6, ny=5, nz=4, hx=1.0, hy=1.5, hz=2.5)
 
 
 def pin_tv_gradient():
-    """dR/df against FP64 central differences of R on a random volume (1e-7 rel)."""
+    """dR/df against FP64 central differences of R on a random volume (1e-6 rel)."""
     f = S.random_volume(TVG, 7) * 0.02
     grad = O.tv_grad(TVG, f, 1e-5)
     h = 1e-7
@@ -445,10 +445,148 @@ def pin_constants():
     return ok, None
 
 
+# ------------------------------------------------------------------ sampled entry points
+def pin_sampled_operators():
+    """The sampled entry points used as references at full size equal the full operators
+    (1e-12): P at selected rays (forward_rays), and P^T at selected voxels (adjoint_voxels, which
+    has its own detector-footprint window), on an anisotropic grid with an off-centre-sized detector
+    and on the 32^3 workload geometry."""
+    out = []
+    for g, seed in ((SMALL, 31), (dataclasses.replace(G1, n_views=5), 33)):
+        x = S.random_volume(g, seed, "normal")
+        y = S.random_projections(g, seed + 1, "normal")
+        rays = np.arange(0, g.n_views * g.nv * g.nu, 5)
+        vox = np.arange(0, g.n_vox, 3)
+        out += [_rel(O.forward_rays(g, x, rays), O.forward(g, x).ravel()[rays]),
+                _rel(O.adjoint_voxels(g, y, vox), O.adjoint(g, y).ravel()[vox])]
+    return max(out) < 1e-12, out
+
+
+# ------------------------------------------------------------------ step size t (Schur bound)
+def pin_schur():
+    """max(P 1) and max(P^T 1) are the largest row and column sums of the dense brute-force matrix
+    (1e-12); their product bounds sigma_max(A)^2 (Schur's test); and the step t is the reciprocal
+    of kappa0 times that bound, kappa0 = 2 N_vox / N_rays being the scale of the normalised gradient
+    N_vox dD/df = kappa0 A^T (A f - Y) (so t kappa0 sigma_max^2 <= 1: Step 1 is a stable gradient step)."""
+    A = brute.matrix(TINY)
+    a, b = O.schur(TINY)
+    ea = abs(a - A.sum(axis=1).max()) / a
+    eb = abs(b - A.sum(axis=0).max()) / b
+    smax2 = np.linalg.norm(A, 2) ** 2
+    kappa0 = 2.0 * A.shape[1] / A.shape[0]
+    t = O.schur_step(TINY)
+    et = abs(t * kappa0 * A.sum(axis=1).max() * A.sum(axis=0).max() - 1.0)
+    ok = ea < 1e-12 and eb < 1e-12 and smax2 <= a * b * (1 + 1e-12) and et < 1e-12 and t * kappa0 * smax2 <= 1 + 1e-12
+    return ok, (ea, eb, smax2 / (a * b), et)
+
+
+# ------------------------------------------------------------------ ROF stop rule
+def pin_rof_stop_rule():
+    """The relative-decrease stop of Step 2 (the paper's 0.1 % rule after Eq. 5): in every ROF loop
+    of a 32^3 solve, each accepted step that is not the loop's last changed E_R by at least 0.1 %;
+    the last record is an accepted step below 0.1 %, a refused search (m = -1) or the 50th iteration."""
+    Y = _cube32_data()
+    res = O.reconstruct(G1, Y, 0.05, [6], 1)
+    tol = GOLD["armijo"]["epsilon_relative"]
+    groups = {}
+    for rec, e in zip(res.trace, res.rof_e):
+        groups.setdefault((int(rec[0]), int(rec[1])), []).append((int(rec[2]), int(rec[3]), e))
+    ok, multi = True, 0
+    for key, recs in groups.items():
+        for n, (inner, m, (e0, enew, _)) in enumerate(recs):
+            rel = abs(enew - e0) / e0
+            if n + 1 < len(recs):
+                ok &= m >= 0 and rel >= tol
+            else:
+                ok &= m == -1 or rel < tol or inner + 1 == O.DEFAULTS["rof_max_iter"]
+        multi += len(recs) > 1
+    return ok and multi > 0 and len(groups) == 6, (len(groups), multi)
+
+
+# ------------------------------------------------------------------ Step-1 scale at lambda > 0
+def pin_lambda_form_fixed_point():
+    """Algorithm A1 minimises D + lambda R: on a tiny problem whose minimiser is positive (so the
+    clamp of Step 3 is inactive), many outer iterations with an accurate Step 2 (rof_tol 1e-14)
+    reach a point where the gradient of E = D + lambda R vanishes: |dD/df + lambda dR/df| <= 1e-6
+    |dD/df|, with dD/df = (2/N_rays) A^T (A f - Y) from the dense brute-force matrix and dR/df by
+    central differences of R.  A wrong Step-1 scale kappa0 (or a wrong weight between the two
+    terms) moves the fixed point to the minimiser of another combination, where this fails."""
+    g = dataclasses.replace(G1, nx=4, ny=4, nz=3, hx=4.0, hy=4.0, hz=4.0, nu=8, nv=6, pu=3.0, pv=3.0, n_views=8)
+    A = brute.matrix(g)
+    rng = np.random.default_rng(21)
+    ftrue = 0.01 + 0.01 * rng.random(g.n_vox)
+    Y = A @ ftrue + 0.0005 * rng.standard_normal(A.shape[0])
+    lam, eps = 0.05, 1e-3
+    res = O.reconstruct(g, Y.reshape(g.proj_shape), lam, [3000], 1, tv_eps=eps, rof_tol=1e-14)
+    f = res.f.ravel()
+    gD = 2.0 / A.shape[0] * A.T @ (A @ f - Y)
+    h = 1e-7
+    gR = np.zeros_like(f)
+    for q in range(f.size):
+        fp = f.copy(); fp[q] += h
+        fm = f.copy(); fm[q] -= h
+        gR[q] = (O.tv_energy(g, fp, eps) - O.tv_energy(g, fm, eps)) / (2 * h)
+    e = float(np.linalg.norm(gD + lam * gR) / np.linalg.norm(gD))
+    return e < 1e-6 and f.min() > 0.0, (e, f.min())
+
+
+# ------------------------------------------------------------------ multigrid level geometry
+def _binned_chords(g, l, half):
+    """Chords through the centred box |x_q| <= half_q of the rays from the source to the centres of
+    the 2^l x 2^l pixel blocks of the level-0 detector (block centre = mean of its pixel centres)."""
+    k = 1 << l
+    ub = ((np.arange(g.nu) - (g.nu - 1) / 2) * g.pu).reshape(-1, k).mean(1)
+    vb = ((np.arange(g.nv) - (g.nv - 1) / 2) * g.pv).reshape(-1, k).mean(1)
+    angles = g.angles if g.angles is not None else 2 * np.pi * np.arange(g.n_views) / g.n_views
+    out = np.zeros((g.n_views, len(vb), len(ub)))
+    for t, th in enumerate(angles):
+        ew = np.array([np.cos(th), np.sin(th), 0.0])
+        eu = np.array([np.sin(th), -np.cos(th), 0.0])
+        src = -g.sad * ew
+        for j, v in enumerate(vb):
+            for i, u in enumerate(ub):
+                d = g.sdd * ew + u * eu + np.array([0.0, 0.0, v])
+                t0, t1 = -np.inf, np.inf
+                for q in range(3):
+                    if d[q] == 0.0:
+                        if abs(src[q]) >= half[q]:
+                            t0, t1 = 1.0, 0.0
+                        continue
+                    a, b = (-half[q] - src[q]) / d[q], (half[q] - src[q]) / d[q]
+                    t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
+                out[t, j, i] = max(t1 - t0, 0.0) * np.linalg.norm(d)
+    return out
+
+
+def pin_level_geometry():
+    """Multigrid levels (Section II.C.3) cover the level-0 box: P_l 1 at levels 1 and 2 of the
+    32^3 workload matches the chord through the level-0 grid box of the rays to the binned pixel
+    centres (8 % and 12 %: the interpolant's one-voxel edge ramp is first order in the coarse
+    pitch); and P_l equals the dense brute-force P of the grid with dims / 2^l, pitch x 2^l,
+    detector binned (pitch x 2^l) and sample spacing min(h_l) (1e-12)."""
+    half = np.array([G1.nx * G1.hx, G1.ny * G1.hy, G1.nz * G1.hz]) / 2
+    ec = []
+    for l in (1, 2):
+        k = 1 << l
+        P1 = O.forward_level(G1, l, np.ones((G1.nz // k, G1.ny // k, G1.nx // k)))
+        ec.append(_rel(P1, _binned_chords(G1, l, half)))
+    T = dataclasses.replace(G1, nx=8, ny=8, nz=4, hx=2.0, hy=2.0, hz=3.0, nu=8, nv=8, pu=3.0, pv=3.0, n_views=3,
+                            angles=(0.2, 1.9, 4.0))
+    eb = []
+    for l in (1, 2):
+        k = 1 << l
+        Tl = dataclasses.replace(T, nx=T.nx // k, ny=T.ny // k, nz=T.nz // k, hx=T.hx * k, hy=T.hy * k,
+                                 hz=T.hz * k, nu=T.nu // k, nv=T.nv // k, pu=T.pu * k, pv=T.pv * k)
+        x = S.random_volume(Tl, 30 + l, "normal")
+        eb.append(_rel(O.forward_level(T, l, x), brute.forward(Tl, x)))
+    return ec[0] < 0.08 and ec[1] < 0.12 and max(eb) < 1e-12, (ec, eb)
+
+
 PINS = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_chords, pin_mass, pin_box,
         pin_centroid, pin_continuum_adjoint, pin_eq6_affine, pin_eq6_near_adjoint, pin_tv_gradient, pin_tv_closed_forms, pin_transfers,
         pin_binning, pin_rof_armijo, pin_fbs_monotone, pin_nnls, pin_resume, pin_constants, pin_convergence_rule,
-        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_sampled, pin_siddon_chords, pin_fbs_siddon]
+        pin_siddon_brute, pin_siddon_box_and_identity, pin_siddon_sampled, pin_siddon_chords, pin_fbs_siddon,
+        pin_sampled_operators, pin_schur, pin_rof_stop_rule, pin_lambda_form_fixed_point, pin_level_geometry]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -472,9 +610,16 @@ FAULTS = {
     11: "voxel grid shifted half a voxel in x",
     12: "Eq. 6 weight without the Jacobian's third power of L",
     13: "Siddon misses the z plane crossings",
+    14: "P^T at sampled voxels: detector footprint window too narrow",
+    15: "ROF relative-decrease stop test disabled",
+    16: "Step 1 scale kappa0 halved",
+    17: "coarse levels keep the level-0 detector pitch",
+    18: "Schur step without the factor 2 of kappa0",
+    19: "coarse levels keep the level-0 sample spacing",
 }
 QUICK = [pin_brute_forward, pin_brute_adjoint, pin_adjoint_identity, pin_centroid, pin_mass, pin_eq6_affine,
-         pin_tv_gradient, pin_tv_closed_forms, pin_transfers, pin_rof_armijo, pin_fbs_monotone, pin_siddon_brute]
+         pin_tv_gradient, pin_tv_closed_forms, pin_transfers, pin_rof_armijo, pin_fbs_monotone, pin_siddon_brute,
+         pin_sampled_operators, pin_schur, pin_rof_stop_rule, pin_lambda_form_fixed_point, pin_level_geometry]
 
 
 @pytest.mark.parametrize("fault", sorted(FAULTS), ids=[FAULTS[k] for k in sorted(FAULTS)])
