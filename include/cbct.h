@@ -23,8 +23,12 @@
  *                sample_ratio * min(hx, hy) at level 0).  w_ij = dtau * |D_ij - S| / |D_ij - S|_xy.
  *   P^T          the exact transpose of P (Section II.C.2: the data-term gradient is
  *                P^T (P f - Y) up to constants), computed by a voxel-driven gather.
+ *   Devices      a context names the HIP device the library works on (the paper's single
+ *                GPU); plans and servers are created from a context and keep its device:
+ *                every call on a plan runs with that device current and restores the
+ *                caller's device before it returns.
  *   Memory       every d_* pointer is device memory on the plan's device, owned by the caller.
- *                The library owns only plans (geometry tables) and servers.  No call
+ *                The library owns only contexts, plans (geometry tables) and servers.  No call
  *                allocates device memory except cbct_plan_create and the server calls.
  *   Streams      every call is asynchronous on `stream` (0 = the null stream) unless stated.
  *   Errors       the status code is the only error channel; nothing aborts or throws across
@@ -68,14 +72,29 @@ typedef struct {
     double sample_ratio;   /* rho: dtau = rho * min(hx, hy); <= 0 means 1 */
 } cbct_geometry_desc;
 
+typedef struct cbct_context cbct_context;
 typedef struct cbct_plan cbct_plan;
 
-/* Builds the geometry tables for `levels` multigrid levels (Section II.C.3) on the current
- * HIP device.  Level l has dims n/2^l over the same box (pitch h*2^l), sample spacing
- * dtau*2^l and, when bin_detector != 0, a detector binned 2^l x 2^l (pitch p*2^l).
- * Errors: INVALID_ARG for non-positive sizes, sad <= half the grid diagonal, sdd <= sad, or
- * dims (and detector dims when binning) not divisible by 2^(levels-1); OUT_OF_MEMORY; HIP. */
-cbct_status cbct_plan_create(const cbct_geometry_desc *geom, int levels, int bin_detector, cbct_plan **out);
+/* The device the reconstruction runs on (the paper runs Algorithm A1 on one GPU, Section
+ * II.C): checks that HIP device `hip_device` exists and is a gfx950 (the only code objects the
+ * library carries) and returns a handle that plans and servers are created from.  The caller
+ * owns it and destroys it after every plan and server made from it (a server keeps a copy of
+ * the device, so it may outlive the context).  Errors: INVALID_ARG for a NULL out, a device
+ * outside [0, device count) or another architecture; HIP; OUT_OF_MEMORY.  No device memory is
+ * allocated. */
+cbct_status cbct_context_create(int hip_device, cbct_context **out);
+void cbct_context_destroy(cbct_context *ctx);
+/* the context's HIP device ordinal */
+cbct_status cbct_context_device(const cbct_context *ctx, int *hip_device);
+
+/* Builds the geometry tables for `levels` multigrid levels (Section II.C.3) on the context's
+ * device.  Level l has dims n/2^l over the same box (pitch h*2^l), sample spacing dtau*2^l and,
+ * when bin_detector != 0, a detector binned 2^l x 2^l (pitch p*2^l).
+ * Errors: INVALID_ARG for a NULL context, non-positive sizes, sad <= half the grid diagonal,
+ * sdd <= sad, or dims (and detector dims when binning) not divisible by 2^(levels-1);
+ * OUT_OF_MEMORY; HIP. */
+cbct_status cbct_plan_create(cbct_context *ctx, const cbct_geometry_desc *geom, int levels, int bin_detector,
+                             cbct_plan **out);
 void cbct_plan_destroy(cbct_plan *plan);
 
 /* dims of a level: out[0..4] = nx, ny, nz, nu, nv; out[5] = n_views */
@@ -156,8 +175,9 @@ cbct_status cbct_adjoint(const cbct_plan *plan, int level, const float *d_proj, 
  * Levels run from params.levels-1 (coarsest, started from 0 or from d_init restricted) to 0,
  * each started from the prolonged solution of the coarser one; t = params.step, or when
  * step <= 0 the Schur bound 1 / (kappa0 max(P_l 1) max(P_l^T 1)) per level (cached in the plan).
- * params.projector picks the pair P, P^T: the trilinear sampling pair (Eq. 4 and its exact
- * adjoint) or the Siddon pair of exact ray-in-voxel lengths (Section II.C.1), everywhere in the
+ * params.projector picks the pair P, P^T: the trilinear sampling pair (the line integral of
+ * Eq. 1 and its exact adjoint) or the Siddon pair of exact ray-in-voxel lengths (the ray tracer
+ * of Section II.C.2), everywhere in the
  * loop (residual, Step 1 and the Schur bound); Siddon with step1_eq6 is the projector and
  * backprojector pair the paper runs. */
 typedef struct {
@@ -171,8 +191,11 @@ typedef struct {
     double rof_tol;         /* relative-decrease stop of Step 2 (default 1e-3) */
     int rof_max_iter;       /* default 50 */
     int rof_max_backtrack;  /* default 30 */
-    const int *replay;      /* NULL, or forced backtracking exponents, one per ROF iteration in order
-                             * (-1: the search finds no step); used up first, then free running */
+    const int *replay;      /* NULL, or a forced decision trace (a test hook for FP32 ties): replay_len
+                             * records of 2 ints, one per ROF iteration in order: the backtracking
+                             * exponent m (-1: the search finds no step) and 1 when that iteration
+                             * ends Step 2 (0: Step 2 goes on), taken in place of the device's
+                             * Armijo and stop decisions; used up first, then free running */
     int replay_len;
     int step1_eq6;          /* 0 (default): Step 1 uses the exact P^T; 1: the Eq. 6 backprojector
                              * (cbct_backproject_eq6) applied to P f - Y, with the same step */
@@ -225,7 +248,10 @@ cbct_status cbct_tv_prox(cbct_plan *plan, int level, const cbct_solve_params *pa
 /* Workspace (device bytes) of cbct_tv_energy_grad (fixed-order partial sums). */
 cbct_status cbct_tv_energy_grad_workspace_size(const cbct_plan *plan, size_t *bytes);
 
-/* Smoothed TV sum S(f) = sum_voxels sqrt(|D f|^2 + tv_eps^2) (= N_vox R(f)) and its gradient
+/* The TV term of the energy (E_1 of Eq. 2, smoothed; forward differences with the boundary
+ * conditions of Section II.B: ghost 0 beyond the last x and y sample, ghost = last plane
+ * beyond the last z plane).
+ * Smoothed TV sum S(f) = sum_voxels sqrt(|D f|^2 + tv_eps^2) (= N_vox R(f)) and its gradient
  * dS/df into d_grad (may be NULL).  h_sum may be NULL; if not, the call synchronises `stream`
  * and writes S.  d_ws: >= cbct_tv_energy_grad_workspace_size bytes, 8-byte aligned. */
 cbct_status cbct_tv_energy_grad(cbct_plan *plan, int level, double tv_eps, const float *d_f, float *d_grad,
@@ -241,8 +267,8 @@ cbct_status cbct_bin_detector(const cbct_plan *plan, int level, const float *d_y
 
 /* ---- Serving: continuous admission of reconstruction requests ----------------------------
  *
- * A server owns `max_slots` worker slots, each with its own non-blocking HIP stream on the device
- * that was current at creation.  Requests (any geometry, any params without replay) queue FIFO;
+ * A server owns `max_slots` worker slots, each with its own non-blocking HIP stream on the
+ * context's device.  Requests (any geometry, any params without replay) queue FIFO;
  * the head starts as soon as a slot is free and (device bytes in use + its bytes) <= the budget,
  * also while other requests run, so admitted solves overlap on the GPU.  A request's bytes are
  * its reconstruction workspace, its plan tables and, for host projections, their device copy.
@@ -251,8 +277,8 @@ cbct_status cbct_bin_detector(const cbct_plan *plan, int level, const float *d_y
  * thread-safe. */
 typedef struct cbct_server cbct_server;
 
-/* INVALID_ARG for budget 0 or max_slots outside 1..256. */
-cbct_status cbct_server_create(size_t hbm_budget_bytes, int max_slots, cbct_server **out);
+/* INVALID_ARG for a NULL context, budget 0 or max_slots outside 1..256. */
+cbct_status cbct_server_create(cbct_context *ctx, size_t hbm_budget_bytes, int max_slots, cbct_server **out);
 
 /* Queue one reconstruction.  y: level-0 projections [n_views][nv][nu], device memory (y_on_host = 0,
  * must stay valid until the request is done) or host memory (y_on_host = 1, copied when the

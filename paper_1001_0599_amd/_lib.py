@@ -53,7 +53,10 @@ class SolveStats(C.Structure):
 # (name, restype, argtypes) of every exported entry point declared in include/cbct.h
 _VP = C.c_void_p
 _SIG = [
-    ("cbct_plan_create", C.c_int, [C.POINTER(GeometryDesc), C.c_int, C.c_int, C.POINTER(_VP)]),
+    ("cbct_context_create", C.c_int, [C.c_int, C.POINTER(_VP)]),
+    ("cbct_context_destroy", None, [_VP]),
+    ("cbct_context_device", C.c_int, [_VP, C.POINTER(C.c_int)]),
+    ("cbct_plan_create", C.c_int, [_VP, C.POINTER(GeometryDesc), C.c_int, C.c_int, C.POINTER(_VP)]),
     ("cbct_plan_destroy", None, [_VP]),
     ("cbct_plan_level_dims", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
     ("cbct_forward_workspace_size", C.c_int, [_VP, C.c_int, C.POINTER(C.c_size_t)]),
@@ -78,7 +81,7 @@ _SIG = [
     ("cbct_prolong", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_restrict", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_bin_detector", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
-    ("cbct_server_create", C.c_int, [C.c_size_t, C.c_int, C.POINTER(_VP)]),
+    ("cbct_server_create", C.c_int, [_VP, C.c_size_t, C.c_int, C.POINTER(_VP)]),
     ("cbct_server_submit", C.c_int, [_VP, C.POINTER(GeometryDesc), C.POINTER(SolveParams), _VP, C.c_int, _VP,
                                      C.POINTER(C.c_uint64)]),
     ("cbct_server_poll", C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -114,6 +117,22 @@ def lib():
                 fn.argtypes = args
             _lib = L
     return _lib
+
+
+_contexts = {}
+
+
+def context(device: int):
+    """The library context of HIP device `device` (cbct_context_create), made once per process
+    and kept until it ends (plans and servers made from it may live as long)."""
+    with _lock:
+        h = _contexts.get(int(device))
+    if h is None:
+        h = C.c_void_p()
+        check(lib().cbct_context_create(int(device), C.byref(h)))
+        with _lock:
+            h = _contexts.setdefault(int(device), h)
+    return h
 
 
 def check(status: int) -> None:

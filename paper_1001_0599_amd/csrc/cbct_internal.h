@@ -103,6 +103,28 @@ struct Level {
     long nray() const { return (long)nviews * nv * nu; }
 };
 
+// A HIP device the library works on: plans and servers are created on it and keep it.
+struct cbct_context {
+    int device = 0;
+    size_t total_mem = 0;
+    char arch[64] = {0};
+};
+
+// Makes `device` current for the lifetime of the guard and restores the caller's device.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int device) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != device) (void)hipSetDevice(device);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+};
+
 struct cbct_plan {
     int device = 0;
     int levels = 1;

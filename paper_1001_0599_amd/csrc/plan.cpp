@@ -195,8 +195,42 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     return CBCT_OK;
 }
 
-extern "C" cbct_status cbct_plan_create(const cbct_geometry_desc *g, int levels, int bin_detector,
-                                        cbct_plan **out) {
+extern "C" cbct_status cbct_context_create(int hip_device, cbct_context **out) {
+    if (!out) return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_create: NULL out");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_create: no HIP device (%s)", hipGetErrorString(e));
+    }
+    if (hip_device < 0 || hip_device >= n)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_create: device %d not in [0, %d)", hip_device, n);
+    hipDeviceProp_t prop;
+    CBCT_HIP(hipGetDeviceProperties(&prop, hip_device));
+    // the library's code objects are built for gfx950 only
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_create: device %d is %s, the library is built for gfx950",
+                              hip_device, prop.gcnArchName);
+    cbct_context *c = new (std::nothrow) cbct_context();
+    if (!c) return cbct_set_error(CBCT_ERR_OUT_OF_MEMORY, "context_create: host allocation");
+    c->device = hip_device;
+    c->total_mem = prop.totalGlobalMem;
+    std::snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+    *out = c;
+    return CBCT_OK;
+}
+
+extern "C" void cbct_context_destroy(cbct_context *ctx) { delete ctx; }
+
+extern "C" cbct_status cbct_context_device(const cbct_context *ctx, int *hip_device) {
+    if (!ctx || !hip_device) return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_device: NULL argument");
+    *hip_device = ctx->device;
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_plan_create(cbct_context *ctx, const cbct_geometry_desc *g, int levels,
+                                        int bin_detector, cbct_plan **out) {
     if (!g || !out) return cbct_set_error(CBCT_ERR_INVALID_ARG, "plan_create: NULL argument");
     *out = nullptr;
     if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->nu <= 0 || g->nv <= 0 || g->n_views <= 0)
@@ -218,9 +252,11 @@ extern "C" cbct_status cbct_plan_create(const cbct_geometry_desc *g, int levels,
     if (g->nv > 2048 || g->nu > 16384)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "plan_create: detector larger than 16384 x 2048");
 
+    if (!ctx) return cbct_set_error(CBCT_ERR_INVALID_ARG, "plan_create: NULL context");
     cbct_plan *p = new (std::nothrow) cbct_plan();
     if (!p) return cbct_set_error(CBCT_ERR_OUT_OF_MEMORY, "plan_create: host allocation");
-    hipGetDevice(&p->device);
+    DeviceGuard dg(ctx->device);
+    p->device = ctx->device;
     p->levels = levels;
     p->bin_detector = bin_detector ? 1 : 0;
     p->lv.resize(levels);
@@ -237,6 +273,7 @@ extern "C" cbct_status cbct_plan_create(const cbct_geometry_desc *g, int levels,
 
 extern "C" void cbct_plan_destroy(cbct_plan *p) {
     if (!p) return;
+    DeviceGuard dg(p->device);
     for (auto &L : p->lv) {
         if (L.d_cols) hipFree(L.d_cols);
         if (L.d_views) hipFree(L.d_views);
@@ -279,6 +316,7 @@ extern "C" cbct_status cbct_forward(const cbct_plan *p, int level, const float *
                                     size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "forward");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_vol || !d_proj || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: NULL pointer");
     const Level &L = p->lv[level];
     if (ws_bytes < (size_t)L.nvox() * sizeof(float))
@@ -304,6 +342,7 @@ extern "C" cbct_status cbct_adjoint(const cbct_plan *p, int level, const float *
                                     size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "adjoint");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_proj || !d_vol || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint: NULL pointer");
     const Level &L = p->lv[level];
     if (ws_bytes < (size_t)L.z_floats * sizeof(float))
@@ -318,6 +357,7 @@ extern "C" cbct_status cbct_forward_columns(const cbct_plan *p, int level, const
                                             cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "forward_columns");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_vol_cols || !d_proj) return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: NULL pointer");
     if (((uintptr_t)d_vol_cols & 15) != 0)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_columns: volume must be 16-byte aligned");
@@ -328,6 +368,7 @@ extern "C" cbct_status cbct_forward_siddon(const cbct_plan *p, int level, const 
                                            void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "forward_siddon");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_vol || !d_proj || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward_siddon: NULL pointer");
     const Level &L = p->lv[level];
     if (ws_bytes < (size_t)L.nvox() * sizeof(float))
@@ -351,6 +392,7 @@ extern "C" cbct_status cbct_adjoint_siddon(const cbct_plan *p, int level, const 
                                            void *d_ws, size_t ws_bytes, cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "adjoint_siddon");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_proj || !d_vol || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "adjoint_siddon: NULL pointer");
     const Level &L = p->lv[level];
     const size_t need = cbct_adjoint_siddon_ws_bytes(L);
@@ -365,6 +407,7 @@ extern "C" cbct_status cbct_backproject_eq6(const cbct_plan *p, int level, const
                                             cbct_stream_t stream) {
     cbct_status s = check_level(p, level, "backproject_eq6");
     if (s) return s;
+    DeviceGuard dg(p->device);
     if (!d_proj || !d_vol) return cbct_set_error(CBCT_ERR_INVALID_ARG, "backproject_eq6: NULL pointer");
     return cbct_launch_backproject_eq6(p->lv[level], d_proj, nullptr, 0.0f, d_vol, (hipStream_t)stream);
 }

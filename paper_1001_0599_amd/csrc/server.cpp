@@ -101,7 +101,7 @@ size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<in
 }  // namespace
 
 struct cbct_server {
-    int device = 0;
+    cbct_context ctx;  // the device the server works on (a copy: the caller's context may go first)
     bool simulated = false;
     size_t budget = 0;
     int max_slots = 1;
@@ -172,7 +172,7 @@ cbct_status get_plan(cbct_server *s, Request *r, cbct_plan **out) {
     cbct_plan *p = nullptr;
     cbct_geometry_desc g = r->g;
     g.angles = r->angles.empty() ? nullptr : r->angles.data();
-    cbct_status st = cbct_plan_create(&g, r->levels, 1, &p);
+    cbct_status st = cbct_plan_create(&s->ctx, &g, r->levels, 1, &p);
     if (st) return st;
     std::lock_guard<std::mutex> lk(s->pool_mu);
     auto it = s->plans.find(key);
@@ -230,7 +230,7 @@ void run_request(cbct_server *s, Request *r, hipStream_t stream) {
 void worker_main(cbct_server *s) {
     hipStream_t stream = nullptr;
     if (!s->simulated) {
-        hipSetDevice(s->device);
+        hipSetDevice(s->ctx.device);
         hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     }
     for (;;) {
@@ -268,15 +268,16 @@ void worker_main(cbct_server *s) {
     if (stream) hipStreamDestroy(stream);
 }
 
-cbct_status server_create(size_t budget, int max_slots, bool sim, cbct_server **out) {
+cbct_status server_create(const cbct_context *ctx, size_t budget, int max_slots, bool sim, cbct_server **out) {
     if (!out || budget == 0 || max_slots < 1 || max_slots > 256)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "server_create: need out, budget > 0 and 1..256 slots");
+    if (!sim && !ctx) return cbct_set_error(CBCT_ERR_INVALID_ARG, "server_create: NULL context");
     auto *s = new (std::nothrow) cbct_server();
     if (!s) return cbct_set_error(CBCT_ERR_OUT_OF_MEMORY, "server_create: host allocation");
     s->simulated = sim;
     s->budget = budget;
     s->max_slots = max_slots;
-    if (!sim) hipGetDevice(&s->device);
+    if (!sim) s->ctx = *ctx;
     for (int w = 0; w < max_slots; w++) s->workers.emplace_back(worker_main, s);
     *out = s;
     return CBCT_OK;
@@ -327,12 +328,13 @@ cbct_status submit(cbct_server *s, const cbct_geometry_desc *g, const cbct_solve
 
 }  // namespace
 
-extern "C" cbct_status cbct_server_create(size_t hbm_budget_bytes, int max_slots, cbct_server **out) {
-    return server_create(hbm_budget_bytes, max_slots, false, out);
+extern "C" cbct_status cbct_server_create(cbct_context *ctx, size_t hbm_budget_bytes, int max_slots,
+                                          cbct_server **out) {
+    return server_create(ctx, hbm_budget_bytes, max_slots, false, out);
 }
 
 extern "C" cbct_status cbct_server_create_simulated(size_t hbm_budget_bytes, int max_slots, cbct_server **out) {
-    return server_create(hbm_budget_bytes, max_slots, true, out);
+    return server_create(nullptr, hbm_budget_bytes, max_slots, true, out);
 }
 
 extern "C" cbct_status cbct_server_submit(cbct_server *s, const cbct_geometry_desc *g, const cbct_solve_params *p,
@@ -409,6 +411,9 @@ extern "C" void cbct_server_destroy(cbct_server *s) {
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
     for (auto &kv : s->plans) cbct_plan_destroy(kv.second);
-    for (void *p : s->owned) hipFree(p);
+    if (!s->owned.empty()) {
+        DeviceGuard dg(s->ctx.device);
+        for (void *p : s->owned) hipFree(p);
+    }
     delete s;
 }

@@ -217,8 +217,13 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
     cbct_status st;
     if (!u_ready) CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < pr->rof_max_iter; it++) {
-        int forced = -2;  // free running
-        if (pr->replay && *replay_pos < pr->replay_len) forced = pr->replay[(*replay_pos)++];
+        int forced = -2;      // free running
+        int forced_end = -1;  // replayed: 1 when this record ends Step 2
+        if (pr->replay && *replay_pos < pr->replay_len) {
+            forced = pr->replay[2 * *replay_pos];
+            forced_end = pr->replay[2 * *replay_pos + 1] != 0 ? 1 : 0;
+            (*replay_pos)++;
+        }
         if ((st = cbct_launch_tv_grad(L, pr->tv_eps, b.u, b.g, b.d, pr->lambda, t, b.part, b.sums, s))) return st;
         RofControl c{};
         if (forced == -1) {
@@ -266,8 +271,8 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
             return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (level %d, outer %d)", level, outer);
         sink.push(level, outer, it, c.accepted == 1 ? c.m : -1, c);
         if (c.accepted != 1) break;  // Eq. 5 held for no step: keep u
-        const bool stop = c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol ||
-                          it + 1 == pr->rof_max_iter;
+        const bool own_stop = c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol;
+        const bool stop = (forced_end >= 0 ? forced_end == 1 : own_stop) || it + 1 == pr->rof_max_iter;
         if (stop && pending) {
             *pending = true;
             break;
@@ -310,6 +315,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
     cbct_status st = check_params(p, pr, "reconstruct");
     if (st) return st;
     if (!d_y || !d_out || !d_ws) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: NULL pointer");
+    DeviceGuard dg(p->device);
     const int levels = pr->levels;
     const int nslots = energy_slots(pr);
     const int proj = pr->projector;
@@ -452,6 +458,7 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
     if (!p || !pr || !d_g || !d_u || !d_ws || level < 0 || level >= p->levels)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: bad arguments");
     if (!(pr->step > 0.0)) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: params.step (t) must be > 0");
+    DeviceGuard dg(p->device);
     Bufs b = carve(p, 1, 1, d_ws);
     if (ws_bytes < b.bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: workspace too small");
     hipStream_t s = (hipStream_t)stream;
@@ -481,6 +488,7 @@ extern "C" cbct_status cbct_tv_energy_grad(cbct_plan *p, int level, double tv_ep
     if (ws_bytes < need) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad: workspace < %zu bytes", need);
     const Level &L = p->lv[level];
     hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(p->device);
     double *part = (double *)d_ws, *sums = part + CBCT_RED_BLOCKS * 3;
     cbct_status st;
     if (d_grad) st = cbct_launch_tv_grad(L, tv_eps, d_f, nullptr, d_grad, 0.0, 1.0, part, sums, s);
@@ -497,6 +505,7 @@ extern "C" cbct_status cbct_prolong(const cbct_plan *p, int coarse_level, const 
                                     cbct_stream_t stream) {
     if (!p || !d_c || !d_f || coarse_level < 1 || coarse_level >= p->levels)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "prolong: bad arguments");
+    DeviceGuard dg(p->device);
     return cbct_launch_prolong(p->lv[coarse_level], d_c, d_f, (hipStream_t)stream);
 }
 
@@ -504,6 +513,7 @@ extern "C" cbct_status cbct_restrict(const cbct_plan *p, int fine_level, const f
                                      cbct_stream_t stream) {
     if (!p || !d_c || !d_f || fine_level < 0 || fine_level + 1 >= p->levels)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "restrict: bad arguments");
+    DeviceGuard dg(p->device);
     return cbct_launch_restrict(p->lv[fine_level + 1], d_f, d_c, (hipStream_t)stream);
 }
 
@@ -511,5 +521,6 @@ extern "C" cbct_status cbct_bin_detector(const cbct_plan *p, int level, const fl
                                          cbct_stream_t stream) {
     if (!p || !d_y0 || !d_yl || level < 1 || level >= p->levels || !p->bin_detector)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "bin_detector: bad arguments (level >= 1, plan with binning)");
+    DeviceGuard dg(p->device);
     return cbct_launch_bin(p->lv[0], 1 << level, d_y0, d_yl, (hipStream_t)stream);
 }

@@ -7,7 +7,7 @@ import torch
 
 import numpy as np
 
-from ._lib import GeometryDesc, SolveParams, SolveStats, check, lib
+from ._lib import GeometryDesc, SolveParams, SolveStats, check, context, lib
 
 
 def _stream_handle(device) -> int:
@@ -46,7 +46,7 @@ class Plan:
                          C.cast(self._angles, C.POINTER(C.c_double)) if self._angles is not None else None,
                          float(getattr(geom, "sample_ratio", 1.0)))
         h = C.c_void_p()
-        check(L.cbct_plan_create(C.byref(d), self.levels, int(self.binned), C.byref(h)))
+        check(L.cbct_plan_create(context(self.device.index), C.byref(d), self.levels, int(self.binned), C.byref(h)))
         self._h = h
         self._dims = []
         for lvl in range(self.levels):
@@ -186,7 +186,9 @@ class Plan:
             setattr(p, k, type(getattr(p, k))(v))
         rp = None
         if replay is not None:
-            rp = (C.c_int * max(len(replay), 1))(*[int(v) for v in replay])
+            # records (m, ends_step2)
+            flat = [int(v) for rec in replay for v in (rec[0], rec[1])]
+            rp = (C.c_int * max(len(flat), 2))(*flat)
             p.replay = C.cast(rp, C.POINTER(C.c_int))
             p.replay_len = len(replay)
         return p, (it, rp)

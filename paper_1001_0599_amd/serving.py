@@ -8,7 +8,7 @@ import time
 
 import numpy as np
 
-from ._lib import GeometryDesc, check, lib
+from ._lib import GeometryDesc, check, context, lib
 
 
 def _desc(g):
@@ -27,8 +27,12 @@ class Server:
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 8, simulated: bool = False):
         self.simulated = simulated
         h = C.c_void_p()
-        fn = lib().cbct_server_create_simulated if simulated else lib().cbct_server_create
-        check(fn(C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
+        if simulated:
+            check(lib().cbct_server_create_simulated(C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
+        else:
+            import torch
+            ctx = context(torch.cuda.current_device())
+            check(lib().cbct_server_create(ctx, C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
         self._h = h
         self._keep = {}
 

@@ -33,3 +33,19 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+def pytest_terminal_summary(terminalreporter):
+    # how often the solver parity tests needed the oracle's decisions replayed (FP32 ties)
+    mod = sys.modules.get("tests.test_gpu_solver")
+    if mod is None or not hasattr(mod, "REPLAYS"):
+        return
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+    except Exception:  # pragma: no cover
+        return
+    terminalreporter.write_line("solver parity: %d solve(s) replayed an FP32 tie" % len(mod.REPLAYS))
+    for shape, iters, q, n, margin in mod.REPLAYS:
+        terminalreporter.write_line("  %s iters %s: record %d of %d, oracle margin %.2e" % (shape, iters, q, n, margin))

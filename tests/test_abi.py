@@ -44,7 +44,7 @@ def _desc(**kw):
 def test_plan_rejects_bad_geometry(bad):
     L = _lib.lib()
     h = C.c_void_p()
-    st = L.cbct_plan_create(C.byref(_desc(**bad)), 1, 1, C.byref(h))
+    st = L.cbct_plan_create(None, C.byref(_desc(**bad)), 1, 1, C.byref(h))
     assert st == 1 and not h.value
     assert L.cbct_last_error()
 
@@ -52,9 +52,30 @@ def test_plan_rejects_bad_geometry(bad):
 def test_plan_rejects_indivisible_levels():
     L = _lib.lib()
     h = C.c_void_p()
-    assert L.cbct_plan_create(C.byref(_desc(nx=30)), 3, 1, C.byref(h)) == 1
+    assert L.cbct_plan_create(None, C.byref(_desc(nx=30)), 3, 1, C.byref(h)) == 1
     assert b"divisible" in L.cbct_last_error()
-    assert L.cbct_plan_create(None, 1, 1, C.byref(h)) == 1
+    assert L.cbct_plan_create(None, None, 1, 1, C.byref(h)) == 1
+
+
+def test_plan_and_server_need_a_context():
+    # a valid geometry without a context is rejected before any device is touched
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.cbct_plan_create(None, C.byref(_desc()), 1, 1, C.byref(h)) == 1
+    assert b"context" in L.cbct_last_error() and not h.value
+    assert L.cbct_server_create(None, C.c_size_t(1 << 30), 2, C.byref(h)) == 1
+    assert not h.value
+
+
+def test_context_rejects_bad_device():
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.cbct_context_create(-1, C.byref(h)) == 1 and not h.value
+    assert L.cbct_context_create(1 << 20, C.byref(h)) == 1 and not h.value
+    assert L.cbct_context_create(0, None) == 1
+    d = C.c_int()
+    assert L.cbct_context_device(None, C.byref(d)) == 1
+    L.cbct_context_destroy(None)  # a no-op
 
 
 def test_calls_reject_null_plan():

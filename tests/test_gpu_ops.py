@@ -161,3 +161,23 @@ def test_input_validation():
     assert L.cbct_forward(plan.handle, 1, x.data_ptr(), y.data_ptr(), x.data_ptr(), 4 * x.numel(), None) == 1
     assert L.cbct_forward(plan.handle, 0, x.data_ptr(), y.data_ptr(), x.data_ptr(), 16, None) == 1
     assert L.cbct_adjoint(plan.handle, -1, y.data_ptr(), x.data_ptr(), None, 0, None) == 1
+
+
+def test_context_binds_plans_to_its_device():
+    """cbct_context_create: device 0 is accepted and recorded, a device past the count is
+    rejected with INVALID_ARG, and a plan made from the context runs P on that device."""
+    import ctypes as C
+    from paper_1001_0599_amd import _lib
+    announce("context create / bad device")
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.cbct_context_create(torch.cuda.device_count(), C.byref(h)) == 1 and not h.value
+    assert b"device" in L.cbct_last_error()
+    assert L.cbct_context_create(0, C.byref(h)) == 0 and h.value
+    d = C.c_int(-1)
+    assert L.cbct_context_device(h, C.byref(d)) == 0 and d.value == 0
+    L.cbct_context_destroy(h)
+    g = CASES["tiny"]
+    plan = _plan(g)
+    vol = S.random_volume(g, 3)
+    assert rel_l2(to_np(plan.forward(to_gpu(vol))), O.forward(g, vol)) < TOL

@@ -2,10 +2,11 @@
 
 Bars: TV energy and gradient, transfers: relative L2 <= 1e-5 (FP32 stencils vs FP64);
 ROF decisions (integer backtracking exponents) identical; volumes after an outer-iteration
-budget: relative L2 <= 1e-3.  When a GPU decision differs from the oracle's, the GPU run is
-repeated with the oracle's decisions replayed; the test then checks that the oracle's margin
-at the first differing decision was tiny (an FP32 tie, not a bug) and applies the 1e-3 bar to
-the replayed run."""
+budget: relative L2 <= 1e-3.  When a GPU decision differs from the oracle's, the test checks
+that the oracle's margin at the first differing decision is below 1e-6 of E_0 (an FP32 tie,
+not a bug), repeats the GPU run with the oracle's decisions replayed (backtracking exponent and
+end of Step 2 per record), requires the replayed trace to equal the oracle's, and applies the
+1e-3 bar to that run.  Every replay is printed and counted."""
 import dataclasses
 
 import numpy as np
@@ -81,6 +82,41 @@ def test_rof_alone_matches_oracle():
         assert rel_l2(to_np(u), res.f) < 1e-5, t
 
 
+# A decision that differs from the oracle's is an FP32 tie only when the oracle's own margin at it
+# is below this (relative to E_0): the GPU's energies are FP64 sums of FP32 values, within about
+# 1e-7 relative of the oracle's on the same decision sequence, so a genuine tie sits an order of
+# magnitude inside it and a decision bug far outside.
+TIE_MARGIN = 1e-6
+# how often replay was needed, per test (reported at the end of the session by conftest)
+REPLAYS = []
+
+
+def replay_records(trace):
+    """(m, ends Step 2) per ROF record of a decision trace (level, outer, inner, m)."""
+    out = []
+    for q, r in enumerate(trace):
+        last = q + 1 == len(trace) or tuple(trace[q + 1][:2]) != tuple(r[:2])
+        out.append((int(r[3]), 1 if last else 0))
+    return out
+
+
+def _margins(res, q, c=0.01, alpha=0.6, tol=1e-3):
+    """The oracle's margins at a first divergence q: the Armijo test of record q (relative to
+    E_0) and the stop test of record q - 1 (|relative decrease - tol|), the one that decided
+    whether record q belongs to the same Step 2 on both sides."""
+    m = []
+    if q < len(res.trace):
+        e0, enew, G = res.rof_e[q]
+        mq = res.trace[q][3]
+        t = res.t_used[res.trace[q][0]]
+        if mq >= 0:
+            m.append(abs((e0 - c * t * alpha ** mq * G) - enew) / e0)
+    if q > 0:
+        e0, enew, _ = res.rof_e[q - 1]
+        m.append(abs(abs(enew - e0) / e0 - tol))
+    return m
+
+
 def _compare_solve(g, Y, lam, iters, levels, step=0.0, **kw):
     """Run oracle and GPU; compare decision traces and volumes (replaying on a tie)."""
     res = O.reconstruct(g, Y, lam, iters, levels, step=step, **kw)
@@ -90,27 +126,21 @@ def _compare_solve(g, Y, lam, iters, levels, step=0.0, **kw):
     q = _first_divergence(st["trace"], res.trace)
     replayed = False
     if q is not None:
-        # the oracle's margin at the first differing decision must be an FP32 tie: the Armijo
-        # test of record q, or the stop test of record q - 1 when one side ended the outer
-        # iteration there and the other went on
-        margins = []
-        if q < len(res.trace):
-            e0, enew, G = res.rof_e[q]
-            m = res.trace[q][3]
-            t = res.t_used[res.trace[q][0]]
-            margins.append(abs((e0 - 0.01 * t * 0.6 ** max(m, 0) * G) - enew) / e0)
-            margins.append(abs(abs(enew - e0) / e0 - 1e-3) / 1e-3)
-        if q > 0:
-            e0, enew, _ = res.rof_e[q - 1]
-            margins.append(abs(abs(enew - e0) / e0 - 1e-3) / 1e-3)
-        assert min(margins) < 1e-4, ("decision diverged with a large margin", q, margins,
-                                     st["trace"][q] if q < len(st["trace"]) else None,
-                                     res.trace[q] if q < len(res.trace) else None,
-                                     rel_l2(got, res.f))
-        f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True,
-                                 replay=[int(r[3]) for r in res.trace], **kw)
+        margins = _margins(res, q)
+        assert margins and min(margins) < TIE_MARGIN, (
+            "decision diverged with a large margin", q, margins,
+            st["trace"][q] if q < len(st["trace"]) else None, res.trace[q] if q < len(res.trace) else None,
+            rel_l2(got, res.f))
+        rec = replay_records(res.trace)
+        f, st = plan.reconstruct(to_gpu(Y), lam=lam, iters=iters, step=step, stats=True, replay=rec, **kw)
         got = to_np(f)
+        # the replayed run takes exactly the oracle's decisions, every one of them
+        assert [tuple(r) for r in st["trace"]] == [tuple(r) for r in res.trace]
+        assert st["replay_used"] == len(res.trace)
         replayed = True
+        REPLAYS.append((g.vol_shape, tuple(iters), q, len(res.trace), min(margins)))
+        print("[replay] %s iters %s: first divergence at record %d of %d, oracle margin %.2e"
+              % (g.vol_shape, tuple(iters), q, len(res.trace), min(margins)), flush=True)
     e = rel_l2(got, res.f)
     return e, replayed, res, st
 
