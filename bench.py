@@ -59,9 +59,15 @@ def measured_traffic():
         return None, None
 
 
-def cpu_baseline(g):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload: P and P^T of 12 of
-    the 40 views (every ray of those views, the full volume), scaled to voxel*views/s."""
+def cpu_baseline(g, iters, lam):
+    """The FP64 oracle on the host cores, on bounded samples of the workload:
+    - all threads: P and P^T of 12 of the 40 views (every ray of those views, the full volume),
+      scaled to voxel*views/s (`value`);
+    - one thread: P and P^T of 2 of the 40 views, the same scaling (`value_1thread`);
+    - the oracle's whole reconstruction ([20, 20] outer iterations, both levels), extrapolated
+      from timed pieces on all threads: per level, P and P^T of the level (the fine level from
+      the 12-view sample scaled to 40 views, the coarse level over all 40 views) plus one ROF
+      solve (Step 2) of the level's volume, times the level's outer iterations."""
     import dataclasses
 
     import numpy as np
@@ -69,27 +75,93 @@ def cpu_baseline(g):
     import cbct_synth as S
     import oracle
 
-    nv = 12
-    g1 = dataclasses.replace(g, n_views=nv, angles=tuple(2 * np.pi * (q * g.n_views // nv) / g.n_views for q in range(nv)))
-    x = S.random_volume(g1, 1)
-    y = S.random_projections(g1, 2)
+    def sample(gg, nv):
+        return dataclasses.replace(gg, n_views=nv, angles=tuple(2 * np.pi * (q * gg.n_views // nv) / gg.n_views
+                                                               for q in range(nv)))
+
+    def time_pair(gg):
+        x = S.random_volume(gg, 1)
+        y = S.random_projections(gg, 2)
+        t0 = time.perf_counter()
+        oracle.forward(gg, x)
+        t1 = time.perf_counter()
+        oracle.adjoint(gg, y)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
     oracle.lib()
-    t0 = time.perf_counter()
-    oracle.forward(g1, x)
-    t1 = time.perf_counter()
-    oracle.adjoint(g1, y)
-    t2 = time.perf_counter()
+    threads = oracle.get_threads()
+    nv = 12
+    tp, ta = time_pair(sample(g, nv))
     vv = g.n_vox * nv
-    return {"value": 2 * vv / (t2 - t0), "unit": "voxel·views/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": "P and P^T of 12 of the 40 views (all 196608 rays each, full 512x512x64 volume), FP64; "
-                      "P %.2f s, P^T %.2f s" % (t1 - t0, t2 - t1)}
+    res = {"value": 2 * vv / (tp + ta), "unit": "voxel·views/s", "cores": threads, "kind": "oracle",
+           "sample": "P and P^T of 12 of the 40 views (all 196608 rays each, full 512x512x64 volume), FP64; "
+                     "P %.2f s, P^T %.2f s" % (tp, ta)}
+    # one thread, 2 views
+    oracle.set_threads(1)
+    try:
+        tp1, ta1 = time_pair(sample(g, 2))
+    finally:
+        oracle.set_threads(threads)
+    res["value_1thread"] = 2 * g.n_vox * 2 / (tp1 + ta1)
+    res["sample_1thread"] = "P and P^T of 2 of the 40 views on 1 thread: P %.2f s, P^T %.2f s" % (tp1, ta1)
+    # extrapolated oracle reconstruction
+    per_level = []
+    for lvl, it in enumerate(iters):
+        gl = S.level_geometry(g, lvl)
+        if lvl == 0:
+            pt = (tp + ta) * g.n_views / nv
+        else:
+            a, b = time_pair(gl)
+            pt = a + b
+        f = np.clip(S.random_volume(gl, 3) * 0.02, 0.0, None)
+        t0 = time.perf_counter()
+        r = oracle.rof(gl, f, lam, 1e-3)
+        rof_s = time.perf_counter() - t0
+        per_level.append((lvl, it, pt, rof_s, len(r.trace)))
+    total = sum(it * (pt + rof_s) for _, it, pt, rof_s, _ in per_level)
+    res["recon_s_extrapolated"] = total
+    res["recon_extrapolation"] = (
+        "EXTRAPOLATED, not run: sum over levels of iters x (P + P^T + one Step-2 solve), each timed once on %d "
+        "threads: " % threads + "; ".join("level %d: %d x (%.2f s + %.2f s for %d ROF iterations)"
+                                          % (lvl, it, pt, rof_s, n) for lvl, it, pt, rof_s, n in per_level))
+    return res
+
+
+def plain_replay(arrivals, reqs, make):
+    """The plain one-at-a-time solver on the same GPU: requests in arrival order, each solved by
+    cbct_reconstruct (plans cached per geometry, like the server's) as soon as it has arrived and
+    the previous one is done.  Returns latencies (completion - arrival) and the span."""
+    import numpy as np
+    import torch
+
+    from paper_1001_0599_amd.ops import Plan
+
+    plans = {}
+    t0 = time.perf_counter()
+    done = np.zeros(len(arrivals))
+    for r, ta in enumerate(arrivals):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        kw = make(r)
+        g = kw["geom"]
+        key = (g.nx, g.ny, g.nz, g.n_views, g.nu, g.nv)
+        if key not in plans:
+            plans[key] = Plan(g)
+        plans[key].reconstruct(kw["y"], lam=kw["lam"], iters=kw["iters"], out=kw["out"])
+        torch.cuda.synchronize()
+        done[r] = time.perf_counter() - t0
+    lat = done - np.asarray(arrivals)
+    return lat, float(done.max() - arrivals[0])
 
 
 def serving_run(n_requests):
     """The serving workload: n requests with Poisson arrivals (4/s), volumes uniform over
     {64^3, 128^3, 256x256x96} at 2 mm, 20-120 views, detector 2Nx x 2Nz at 1.5 mm, 30 iterations,
-    200 GB budget; the continuous-admission server (8 slots) against the one-at-a-time solver
-    (1 slot) on the same arrivals, then both with all requests submitted at once (saturation)."""
+    200 GB budget; the continuous-admission server (8 slots, batched engines) against the plain
+    solver one request at a time on the same arrivals, then both with all requests submitted at
+    once (saturation).  Served results are checked bitwise against the plain ones."""
     import numpy as np
     import torch
 
@@ -99,31 +171,39 @@ def serving_run(n_requests):
     cfg = S.CONFIGS["serving_mix"]
     reqs = S.serving_requests(n_requests)
     log("serving: synthesising %d requests on the GPU" % n_requests)
-    ys, outs = [], []
+    ys, outs, ref = [], [], []
     for r in reqs:
         g = r["geometry"]
         ph = S.make_phantom(g, r["phantom_seed"])
         p = S.analytic_projections_torch(g, ph, "cuda")
         ys.append(S.poisson_log_torch(p, cfg["I0"], r["noise_seed"]).float().contiguous())
         outs.append(torch.empty(g.vol_shape, device="cuda"))
+        ref.append(torch.empty(g.vol_shape, device="cuda"))
     torch.cuda.synchronize()
     arrivals = np.array([r["arrival"] for r in reqs]) - reqs[0]["arrival"]
 
-    def make(r):
-        return dict(geom=reqs[r]["geometry"], y=ys[r], out=outs[r], lam=cfg["lam"], iters=tuple(cfg["iters"]))
+    def make(dst):
+        return lambda r: dict(geom=reqs[r]["geometry"], y=ys[r], out=dst[r], lam=cfg["lam"],
+                              iters=tuple(cfg["iters"]))
 
     res = {"requests": n_requests, "budget_bytes": cfg["budget_bytes"], "iters": cfg["iters"][0]}
-    for name, slots, arr in (("served", 8, arrivals), ("plain", 1, arrivals),
-                             ("served_saturated", 8, np.zeros_like(arrivals)),
-                             ("plain_saturated", 1, np.zeros_like(arrivals))):
-        log("serving: %s (%d slots)" % (name, slots))
-        srv = Server(budget_bytes=cfg["budget_bytes"], max_slots=slots)
-        # warm the plan cache and pools with the distinct geometries is left out on purpose:
+    for name, arr in (("plain", arrivals), ("plain_saturated", np.zeros_like(arrivals))):
+        log("serving: %s (one at a time)" % name)
+        lat, span = plain_replay(arr, reqs, make(ref))
+        res[name] = summarize(lat, span)
+    for name, arr in (("served", arrivals), ("served_saturated", np.zeros_like(arrivals))):
+        log("serving: %s (8 slots)" % name)
+        srv = Server(budget_bytes=cfg["budget_bytes"], max_slots=8)
         # first-request costs (plan tables, Schur step) are part of serving
-        lat, span, _ = replay(srv, arr, make)
+        lat, span, _ = replay(srv, arr, make(outs))
         st = srv.stats()
+        launches, items = srv.batch_stats()
         srv.close()
-        res[name] = dict(summarize(lat, span), peak_running=st["peak_running"], peak_in_use_gb=st["peak_in_use"] / 1e9)
+        same = all(torch.equal(a, b) for a, b in zip(outs, ref))
+        res[name] = dict(summarize(lat, span), peak_running=st["peak_running"],
+                         peak_device_gb=st["peak_in_use"] / 1e9, batched_launches=launches,
+                         items_per_launch=items / max(launches, 1), bitwise_equal_to_plain=same)
+    res["throughput_gain_saturated"] = res["served_saturated"]["req_per_s"] / res["plain_saturated"]["req_per_s"]
     return res
 
 
@@ -299,7 +379,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=32, metavar="N",
+    ap.add_argument("--serving", type=int, default=256, metavar="N",
                     help="requests of the serving workload to replay (256 in the full workload; 0: skip)")
     ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (for counters)")
     ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "HIT_DIR"),
@@ -471,7 +551,7 @@ def main():
         res["serving"] = serving_run(args.serving)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample)")
-        res["cpu_baseline"] = cpu_baseline(g)
+        res["cpu_baseline"] = cpu_baseline(g, iters, lam)
     print(json.dumps(res), flush=True)
 
 

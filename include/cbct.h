@@ -299,9 +299,15 @@ cbct_status cbct_server_request_times(cbct_server *server, uint64_t ticket, doub
 /* Blocks until the queue is empty and no request runs; returns the first failed request's status. */
 cbct_status cbct_server_wait_all(cbct_server *server);
 
-/* Current and peak device bytes in use, running requests, queue length, completed requests. */
+/* Device bytes the server holds now and at its peak (its pooled blocks, idle ones included, and
+ * its cached plan tables: what it obtained from hipMalloc; never above the budget), running
+ * requests, queue length, completed requests.  A simulated server reports its admission charge. */
 cbct_status cbct_server_stats(cbct_server *server, size_t *in_use, size_t *peak_in_use, int *running,
                               int *peak_running, int *queued, uint64_t *completed);
+
+/* Work the batch engine has done so far: batched launches and the request items they carried
+ * (items / launches > 1 means launches shared by several requests). */
+cbct_status cbct_server_batch_stats(cbct_server *server, uint64_t *launches, uint64_t *items);
 
 /* Stops the workers after their current request (queued requests are dropped) and frees the
  * server's device memory and plans. */

@@ -89,6 +89,7 @@ _SIG = [
     ("cbct_server_wait_all", C.c_int, [_VP]),
     ("cbct_server_stats", C.c_int, [_VP, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
+    ("cbct_server_batch_stats", C.c_int, [_VP, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("cbct_server_destroy", None, [_VP]),
     ("cbct_server_create_simulated", C.c_int, [C.c_size_t, C.c_int, C.POINTER(_VP)]),
     ("cbct_server_submit_simulated", C.c_int, [_VP, C.POINTER(GeometryDesc), C.POINTER(SolveParams), C.c_double,

@@ -193,6 +193,25 @@ struct RofControl {
     int pad;         // in the host-mapped copy: the decision call's sequence number, written last
 };
 
+// Step 2 of a small volume in one work-group (no host round trip per ROF iteration): state and
+// per-iteration records kept in device memory across the outer iterations of a level.
+constexpr long CBCT_SMALL_ROF_VOX = 65536;  // volumes up to this many voxels take that path
+struct RofSmallState {
+    int n_rec;       // records appended so far (also those beyond the buffer)
+    int replay_pos;  // replay records consumed
+    int status;      // 1: a non-finite energy stopped the loop
+    int pad;
+};
+struct RofRecord {
+    double e0, e_trial, G;
+    int level, outer, inner, m;  // m = -1: no admissible step
+};
+static_assert(sizeof(RofRecord) == 40, "RofRecord layout");
+cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const float *g, float *d, double lambda,
+                                  double t, double c_armijo, double alpha, double tol, int max_iter, int max_bt,
+                                  const int *replay, int replay_len, int replay_pos, RofSmallState *st,
+                                  RofRecord *rec, int rec_cap, int level, int outer, bool init, hipStream_t s);
+
 int cbct_reduce_blocks(const Level &L);
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s);
@@ -206,6 +225,71 @@ cbct_status cbct_launch_rof_decide(const double *sums, int m0, int M, int forced
                                    RofControl *mirror, int seq, hipStream_t s);
 cbct_status cbct_launch_axpy_step(float *u, const float *d, const RofControl *ctl, long n, hipStream_t s);
 cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *out, hipStream_t s);
+
+// Buffers of a reconstruction carved from its workspace (cbct_reconstruct's layout).
+struct SolveBufs {
+    float *f, *ft, *g, *u, *d, *r, *z;
+    float *ypyr[8];
+    double *part, *sums, *eng;
+    RofControl *ctl;
+    RofSmallState *sst;  // Step 2 on the device for small levels: state and records
+    RofRecord *rec;
+    int rec_cap;
+    int *replay;         // device copy of params.replay (2 ints per record)
+    size_t bytes;
+};
+SolveBufs cbct_solve_carve(const cbct_plan *p, const cbct_solve_params *pr, void *ws);
+// Schur-bound step of a level (cached in the plan)
+cbct_status cbct_solve_schur(cbct_plan *p, int level, int projector, const SolveBufs &b, hipStream_t s, double *t);
+
+// ---- batched launches (the serving engine): one launch carries the work-groups of several
+// requests; each request's work-groups run the solo kernel's body on that request's buffers and
+// grid, so its results are bitwise those of a solo launch.
+constexpr int CBCT_MAXB = 16;  // requests per batched launch
+struct TvReq {                 // one request of a batched TV / ROF launch
+    const Level *L;
+    double eps, lambda, t, alpha;
+    const float *u, *g;
+    float *d;
+    double *partials, *sums;
+    int m0;  // trial passes: first backtracking exponent of the window
+};
+// d, E_R and G sums (grad + fixed-order sum), trial sums of M (1 or CBCT_TRIALS) step sizes
+cbct_status cbct_launch_tv_grad_batch(const TvReq *r, int n, hipStream_t s);
+cbct_status cbct_launch_tv_trial_batch(const TvReq *r, int n, int M, hipStream_t s);
+struct DecideReq {
+    const double *sums;
+    int m0, M;
+    long nvox;
+    double lambda, t, c_armijo, alpha;
+    int max_bt;
+    RofControl *ctl, *mirror;
+    int seq;
+};
+cbct_status cbct_launch_rof_decide_batch(const DecideReq *r, int n, hipStream_t s);
+struct AxpyReq {
+    float *u;
+    const float *d;
+    const RofControl *ctl;
+    long n;
+};
+cbct_status cbct_launch_axpy_batch(const AxpyReq *r, int n, hipStream_t s);
+struct ClampReq {
+    const Level *L;
+    const float *u, *d;
+    const RofControl *ctl;
+    float *f, *f_t;
+};
+cbct_status cbct_launch_clamp_batch(const ClampReq *r, int n, hipStream_t s);
+struct FwdReq {
+    const Level *L;
+    const float *vol_t, *ysub;
+    float *out;
+    double *partials;
+};
+// residual P of several requests; requests whose projector configuration differs from the first
+// one's go to further launches (same stream)
+cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s);
 
 // multigrid transfers and small vector kernels
 cbct_status cbct_launch_prolong(const Level &coarse, const float *c, float *f, hipStream_t s);

@@ -95,15 +95,16 @@ __global__ void __launch_bounds__(256) k_bin(const float *__restrict__ y0, float
 }
 
 // Step 3 (f = max(u, 0)) fused with the copy of f into the projector's column-major layout
-__global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__ u, const float *__restrict__ d,
-                                                       const RofControl *__restrict__ ctl, float *__restrict__ f,
-                                                       float *__restrict__ f_t, int nx, int ny, int nz) {
+__device__ __forceinline__ void clamp_columns_body(const float *__restrict__ u, const float *__restrict__ d,
+                                                   const RofControl *__restrict__ ctl, float *__restrict__ f,
+                                                   float *__restrict__ f_t, int nx, int ny, int nz, int bx, int by,
+                                                   int bz) {
     __shared__ float tile[32][33];
     // a pending accepted ROF step u - s d is applied here (the same product as the update kernel's)
     const bool step = d && ctl->accepted == 1;
     const float st = step ? (float)ctl->s : 0.0f;
-    const int b = blockIdx.z;
-    const int a0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    const int b = bz;
+    const int a0 = bx * 32, c0 = by * 32;
     const int tx = threadIdx.x, ty = threadIdx.y;
     for (int r = ty; r < 32; r += 8) {
         const int c = c0 + r, a = a0 + tx;
@@ -119,6 +120,35 @@ __global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__
         const int a = a0 + r, c = c0 + tx;
         if (a < nx && c < nz) f_t[((long)b * nx + a) * nz + c] = tile[tx][r];
     }
+}
+
+__global__ void __launch_bounds__(256) k_clamp_columns(const float *__restrict__ u, const float *__restrict__ d,
+                                                       const RofControl *__restrict__ ctl, float *__restrict__ f,
+                                                       float *__restrict__ f_t, int nx, int ny, int nz) {
+    clamp_columns_body(u, d, ctl, f, f_t, nx, ny, nz, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// batched Step 3 (serving engine): request q owns work-groups [wg0[q], wg0[q+1]) of a flat grid,
+// each running the solo kernel's body at its place in the request's (nx/32, nz/32, ny) grid
+struct BClItem {
+    const float *u, *d;
+    const RofControl *ctl;
+    float *f, *f_t;
+    int nx, ny, nz, gx, gy;
+};
+struct BCl {
+    int n;
+    int wg0[CBCT_MAXB + 1];
+    BClItem it[CBCT_MAXB];
+};
+
+__global__ void __launch_bounds__(256) k_clamp_columns_b(BCl B) {
+    int r = 0;
+    while (r + 1 < B.n && (int)blockIdx.x >= B.wg0[r + 1]) r++;
+    const BClItem &it = B.it[r];
+    const int local = blockIdx.x - B.wg0[r];
+    const int bx = local % it.gx, rest = local / it.gx;
+    clamp_columns_body(it.u, it.d, it.ctl, it.f, it.f_t, it.nx, it.ny, it.nz, bx, rest % it.gy, rest / it.gy);
 }
 
 __global__ void k_fill(float *__restrict__ x, long n, float v) {
@@ -204,5 +234,26 @@ cbct_status cbct_launch_max(const float *x, long n, double *partials, double *ou
     LAUNCH_CHECK("k_max_part");
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partials, nb, out);
     LAUNCH_CHECK("k_max_final");
+    return CBCT_OK;
+}
+
+cbct_status cbct_launch_clamp_batch(const ClampReq *r, int n, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
+        const int m = std::min(CBCT_MAXB, n - q0);
+        BCl B{};
+        B.n = m;
+        int w = 0;
+        for (int q = 0; q < m; q++) {
+            const ClampReq &c = r[q0 + q];
+            const Level &L = *c.L;
+            const int gx = (L.nx + 31) / 32, gy = (L.nz + 31) / 32;
+            B.it[q] = BClItem{c.u, c.d, c.ctl, c.f, c.f_t, L.nx, L.ny, L.nz, gx, gy};
+            B.wg0[q] = w;
+            w += gx * gy * L.ny;
+        }
+        B.wg0[m] = w;
+        hipLaunchKernelGGL(k_clamp_columns_b, dim3(w), dim3(32, 8), 0, s, B);
+        LAUNCH_CHECK("k_clamp_columns_b");
+    }
     return CBCT_OK;
 }

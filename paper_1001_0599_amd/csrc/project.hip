@@ -236,10 +236,10 @@ __host__ __device__ constexpr size_t runs_lds_bytes(int nz, int nwaves) {
 }
 
 template <int KC, int NPT>
-__global__ void __launch_bounds__(256)
-    k_forward_runs(const float *__restrict__ vol_t, const ColParams *__restrict__ cols, int nx, int ny, int nz, int nu,
-                   int nv, float pv, const float *__restrict__ ysub, int wres, float *__restrict__ out,
-                   double *__restrict__ partials) {
+__device__ __forceinline__ void forward_runs_body(const float *__restrict__ vol_t, const ColParams *__restrict__ cols,
+                                                  int nx, int ny, int nz, int nu, int nv, float pv,
+                                                  const float *__restrict__ ysub, int wres, float *__restrict__ out,
+                                                  double *__restrict__ partials, int i, int view) {
     extern __shared__ float4 lds4[];
     constexpr int S = KC + 1;  // entries per cell: (A, K) before local sample k = 0 .. KC
     const int tw = nz + 2;
@@ -249,8 +249,6 @@ __global__ void __launch_bounds__(256)
     float2 *tot = reinterpret_cast<float2 *>(ko + KC);  // [wave][nz]: slice totals
     __shared__ double wsum[4];
 
-    const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int i = w % nu, view = w / nu;
     const ColParams cp = cols[(long)view * nu + i];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
@@ -430,6 +428,51 @@ __global__ void __launch_bounds__(256)
 }
 
 template <int KC, int NPT>
+__global__ void __launch_bounds__(256)
+    k_forward_runs(const float *__restrict__ vol_t, const ColParams *__restrict__ cols, int nx, int ny, int nz, int nu,
+                   int nv, float pv, const float *__restrict__ ysub, int wres, float *__restrict__ out,
+                   double *__restrict__ partials) {
+    // adjacent columns of one view sweep nearly the same voxels: keep them on one XCD
+    const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    forward_runs_body<KC, NPT>(vol_t, cols, nx, ny, nz, nu, nv, pv, ysub, wres, out, partials, w % nu, w / nu);
+}
+
+// batched residual P (serving engine): request q owns work-groups [wg0[q], wg0[q+1]), one per
+// (view, column) of its own geometry, all with the same chunk, rows per thread and block size
+struct BFwItem {
+    const float *vol_t;
+    const ColParams *cols;
+    const float *ysub;
+    float *out;
+    double *partials;
+    int nx, ny, nz, nu, nv;
+    float pv;
+};
+struct BFw {
+    int n;
+    int wg0[CBCT_MAXB + 1];
+    BFwItem it[CBCT_MAXB];
+};
+
+template <int KC, int NPT>
+__global__ void __launch_bounds__(256) k_forward_runs_b(BFw B) {
+    int r = 0;
+    while (r + 1 < B.n && (int)blockIdx.x >= B.wg0[r + 1]) r++;
+    const BFwItem &it = B.it[r];
+    const int w = blockIdx.x - B.wg0[r];
+    forward_runs_body<KC, NPT>(it.vol_t, it.cols, it.nx, it.ny, it.nz, it.nu, it.nv, it.pv, it.ysub, 1, it.out,
+                               it.partials, w % it.nu, w / it.nu);
+}
+
+template <int KC, int NPT>
+cbct_status launch_fwd_runs_b(const BFw &B, size_t lds, int block, hipStream_t s) {
+    hipLaunchKernelGGL((k_forward_runs_b<KC, NPT>), dim3(B.wg0[B.n]), dim3(block), lds, s, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cbct_hip_error(e, "k_forward_runs_b launch");
+    return CBCT_OK;
+}
+
+template <int KC, int NPT>
 cbct_status launch_fwd_runs(const Level &L, const float *vol_t, const float *ysub, int wres, float *out,
                             double *partials, hipStream_t s, int block) {
     const size_t lds = runs_lds_bytes<KC>(L.nz, block / 64);
@@ -524,4 +567,69 @@ cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float 
     }
 #undef CBCT_FWD
     return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: %d detector rows is more than supported", L.nv);
+}
+
+// the run-summing projector's configuration of a level: chunk, row pairs per thread, block size
+static bool fwd_runs_config(const Level &L, int &kc, int &npt, int &block) {
+    if (L.fwd_kr <= 0) return false;
+    const int npairs = (L.nv + 1) / 2;
+    npt = 1;
+    while ((npairs + npt - 1) / npt > 256) npt *= 2;
+    block = (((npairs + npt - 1) / npt + 63) / 64) * 64;
+    kc = L.fwd_kr;
+    return npt <= 8;
+}
+
+cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s) {
+    std::vector<bool> done(n, false);
+    for (int q = 0; q < n; q++) {
+        if (done[q]) continue;
+        int kc, npt, block;
+        if (!fwd_runs_config(*r[q].L, kc, npt, block)) {
+            // per-sample projector: a launch of its own
+            done[q] = true;
+            cbct_status st = cbct_launch_forward(*r[q].L, r[q].vol_t, r[q].ysub, r[q].out, r[q].partials, s, true);
+            if (st) return st;
+            continue;
+        }
+        // every remaining request with the same configuration, up to CBCT_MAXB per launch
+        BFw B{};
+        size_t lds = 0;
+        int w = 0;
+        for (int q2 = q; q2 < n && B.n < CBCT_MAXB; q2++) {
+            int kc2, npt2, block2;
+            if (done[q2] || !fwd_runs_config(*r[q2].L, kc2, npt2, block2) || kc2 != kc || npt2 != npt ||
+                block2 != block)
+                continue;
+            done[q2] = true;
+            const Level &L = *r[q2].L;
+            B.it[B.n] = BFwItem{r[q2].vol_t, L.d_cols, r[q2].ysub, r[q2].out, r[q2].partials, L.nx, L.ny, L.nz,
+                                L.nu, L.nv, (float)L.pv};
+            B.wg0[B.n] = w;
+            w += L.nu * L.nviews;
+            B.n++;
+            size_t l2 = 0;
+            switch (kc) {
+                case 64: l2 = runs_lds_bytes<64>(L.nz, block / 64); break;
+                case 32: l2 = runs_lds_bytes<32>(L.nz, block / 64); break;
+                case 16: l2 = runs_lds_bytes<16>(L.nz, block / 64); break;
+                default: l2 = runs_lds_bytes<8>(L.nz, block / 64); break;
+            }
+            lds = std::max(lds, l2);
+        }
+        B.wg0[B.n] = w;
+        cbct_status st = CBCT_OK;
+#define CBCT_FWB(KC_)                                                           \
+    if (npt == 1) st = launch_fwd_runs_b<KC_, 1>(B, lds, block, s);             \
+    else if (npt == 2) st = launch_fwd_runs_b<KC_, 2>(B, lds, block, s);        \
+    else if (npt == 4) st = launch_fwd_runs_b<KC_, 4>(B, lds, block, s);        \
+    else st = launch_fwd_runs_b<KC_, 8>(B, lds, block, s);
+        if (kc == 64) { CBCT_FWB(64) }
+        else if (kc == 32) { CBCT_FWB(32) }
+        else if (kc == 16) { CBCT_FWB(16) }
+        else { CBCT_FWB(8) }
+#undef CBCT_FWB
+        if (st) return st;
+    }
+    return CBCT_OK;
 }

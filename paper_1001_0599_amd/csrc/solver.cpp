@@ -74,6 +74,9 @@ bool poll_seq(const RofControl *rec, int seq) {
 
 std::mutex g_schur_mu;
 
+// device-side records of cbct_tv_prox's Step 2 (one per ROF iteration, the default cap of 50 fits)
+constexpr int TV_PROX_REC = 64;
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Carver {
@@ -87,13 +90,7 @@ struct Carver {
     }
 };
 
-struct Bufs {
-    float *f, *ft, *g, *u, *d, *r, *z;
-    float *ypyr[8];
-    double *part, *sums, *eng;
-    RofControl *ctl;
-    size_t bytes;
-};
+using Bufs = SolveBufs;
 
 size_t partial_count(const cbct_plan *p) {
     size_t m = (size_t)CBCT_RED_BLOCKS * (3 + 2 * CBCT_TRIALS);
@@ -101,7 +98,16 @@ size_t partial_count(const cbct_plan *p) {
     return m;
 }
 
-Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws, int projector = 0) {
+// records of the device-side Step 2: at most rof_max_iter per outer iteration of a small level
+int small_rec_cap(const cbct_plan *p, const cbct_solve_params *pr) {
+    long cap = 0;
+    for (int l = 0; l < pr->levels; l++)
+        if (p->lv[l].nvox() <= CBCT_SMALL_ROF_VOX) cap = std::max(cap, (long)std::max(pr->iters[l], 1) * pr->rof_max_iter);
+    return (int)std::min<long>(cap, 1L << 24);
+}
+
+Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws, int projector = 0, int rec_cap = 0,
+          int replay_len = 0) {
     Carver c{(char *)ws};
     const Level &L0 = p->lv[0];
     Bufs b{};
@@ -123,6 +129,10 @@ Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws, int proje
     b.sums = c.take<double>(64);
     b.eng = c.take<double>(2 * (size_t)std::max(energy_slots, 1));
     b.ctl = c.take<RofControl>(1);
+    b.sst = c.take<RofSmallState>(1);
+    b.rec_cap = rec_cap;
+    b.rec = c.take<RofRecord>(std::max(rec_cap, 1));
+    b.replay = c.take<int>(2 * (size_t)std::max(replay_len, 1));
     b.bytes = c.off;
     return b;
 }
@@ -207,6 +217,30 @@ struct TraceSink {
     }
 };
 
+// Reads back the device-side Step 2 of a small level: its state (replay records consumed, a
+// non-finite energy) and, for the caller's statistics, its per-iteration records in order.
+cbct_status flush_small(const Bufs &b, hipStream_t s, TraceSink &sink, int *replay_pos) {
+    RofSmallState st;
+    CBCT_HIP(hipMemcpyAsync(&st, b.sst, sizeof(st), hipMemcpyDeviceToHost, s));
+    CBCT_HIP(hipStreamSynchronize(s));
+    if (replay_pos) *replay_pos = st.replay_pos;
+    const int n = std::min(st.n_rec, b.rec_cap);
+    if (sink.st && n > 0) {
+        std::vector<RofRecord> rec(n);
+        CBCT_HIP(hipMemcpyAsync(rec.data(), b.rec, sizeof(RofRecord) * n, hipMemcpyDeviceToHost, s));
+        CBCT_HIP(hipStreamSynchronize(s));
+        for (const RofRecord &r : rec) {
+            RofControl c{};
+            c.e0 = r.e0;
+            c.e_trial = r.e_trial;
+            c.G = r.G;
+            sink.push(r.level, r.outer, r.inner, r.m, c);
+        }
+    }
+    if (st.status) return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (device-side Step 2)");
+    return CBCT_OK;
+}
+
 // Step 2: u = ROF(g) from u = g (u_ready: Step 1 has written u already).  `replay_pos` walks
 // params.replay.  With `pending`, an accepted step that ends the loop is not applied to u; the
 // caller's Step 3 applies it (*pending = true, the step in b.ctl).
@@ -285,6 +319,15 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
 
 }  // namespace
 
+SolveBufs cbct_solve_carve(const cbct_plan *p, const cbct_solve_params *pr, void *ws) {
+    return carve(p, pr->levels, energy_slots(pr), ws, pr->projector, small_rec_cap(p, pr),
+                 pr->replay ? pr->replay_len : 0);
+}
+
+cbct_status cbct_solve_schur(cbct_plan *p, int level, int projector, const SolveBufs &b, hipStream_t s, double *t) {
+    return schur_step(p, level, projector, b, s, t);
+}
+
 extern "C" void cbct_solve_params_default(cbct_solve_params *p) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));
@@ -304,7 +347,8 @@ extern "C" cbct_status cbct_reconstruct_workspace_size(const cbct_plan *p, const
     cbct_status st = check_params(p, pr, "reconstruct_workspace_size");
     if (st) return st;
     if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct_workspace_size: NULL out");
-    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr, pr->projector).bytes;
+    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr, pr->projector, small_rec_cap(p, pr),
+                   pr->replay ? pr->replay_len : 0).bytes;
     return CBCT_OK;
 }
 
@@ -319,7 +363,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
     const int levels = pr->levels;
     const int nslots = energy_slots(pr);
     const int proj = pr->projector;
-    Bufs b = carve(p, levels, nslots, d_ws, proj);
+    Bufs b = carve(p, levels, nslots, d_ws, proj, small_rec_cap(p, pr), pr->replay ? pr->replay_len : 0);
     if (ws_bytes < b.bytes)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: workspace %zu < %zu bytes", ws_bytes, b.bytes);
     if (((uintptr_t)d_ws & 255) != 0)
@@ -332,6 +376,9 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         for (int l = 0; l < 8; l++) stats->t_used[l] = 0.0;
     }
     TraceSink sink{stats};
+    if (pr->replay && pr->replay_len > 0)
+        CBCT_HIP(hipMemcpyAsync(b.replay, pr->replay, sizeof(int) * 2 * (size_t)pr->replay_len, hipMemcpyHostToDevice,
+                                s));
     const bool want_energy = stats && stats->energy;
     const bool conv = pr->conv_tol > 0.0;  // the stop rule needs E(f_k) on the host every iteration
     std::vector<int> slots_of_level(levels, 0);
@@ -372,6 +419,10 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         if (stats) stats->t_used[l] = t;
         const float kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
         if ((st = cbct_launch_to_columns(L, b.f, b.ft, s))) return st;
+        // small levels run Step 2 in one work-group on the device: no host round trip per ROF
+        // iteration (the records and the replay position come back once, at the level's end)
+        const bool small = L.nvox() <= CBCT_SMALL_ROF_VOX && b.rec_cap > 0;
+        bool small_ran = false;
         double e_prev = 0.0;
         for (int k = 0; k <= pr->iters[l]; k++) {
             const bool last = (k == pr->iters[l]);
@@ -411,12 +462,22 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
             if (st) return st;
             // Step 2
             bool pending = false;
-            if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, true, &pending))) return st;
+            if (small) {
+                st = cbct_launch_rof_small(L, pr->tv_eps, b.u, b.g, b.d, pr->lambda, t, pr->armijo_c, pr->backtrack,
+                                           pr->rof_tol, pr->rof_max_iter, pr->rof_max_backtrack,
+                                           pr->replay ? b.replay : nullptr, pr->replay ? pr->replay_len : 0,
+                                           replay_pos, b.sst, stats ? b.rec : nullptr, b.rec_cap, l, k, !small_ran, s);
+                if (st) return st;
+                small_ran = true;
+            } else if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, true, &pending))) {
+                return st;
+            }
             // Step 3 (with the last ROF update when it is pending)
             if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s, pending ? b.d : nullptr,
                                                 pending ? b.ctl : nullptr)))
                 return st;
         }
+        if (small_ran && (st = flush_small(b, s, sink, &replay_pos))) return st;
     }
     CBCT_HIP(hipMemcpyAsync(d_out, b.f, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
     if (stats) {
@@ -448,7 +509,7 @@ extern "C" cbct_status cbct_tv_prox_workspace_size(const cbct_plan *p, int level
     cbct_solve_params_default(&pr);
     int it = 0;
     pr.iters = &it;
-    *bytes = carve(p, 1, 1, nullptr).bytes;
+    *bytes = carve(p, 1, 1, nullptr, 0, TV_PROX_REC).bytes;
     return CBCT_OK;
 }
 
@@ -459,7 +520,7 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: bad arguments");
     if (!(pr->step > 0.0)) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: params.step (t) must be > 0");
     DeviceGuard dg(p->device);
-    Bufs b = carve(p, 1, 1, d_ws);
+    Bufs b = carve(p, 1, 1, d_ws, 0, TV_PROX_REC);
     if (ws_bytes < b.bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_prox: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const Level &L = p->lv[level];
@@ -467,8 +528,18 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
     TraceSink sink{stats};
     int pos = 0;
     CBCT_HIP(hipMemcpyAsync(b.g, d_g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
-    cbct_status st = rof_loop(L, pr, pr->step, b, s, sink, level, 0, &pos);
-    if (st) return st;
+    cbct_status st;
+    if (L.nvox() <= CBCT_SMALL_ROF_VOX && pr->rof_max_iter <= b.rec_cap && !pr->replay) {
+        // the whole loop in one work-group on the device, read back once
+        CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+        if ((st = cbct_launch_rof_small(L, pr->tv_eps, b.u, b.g, b.d, pr->lambda, pr->step, pr->armijo_c, pr->backtrack,
+                                        pr->rof_tol, pr->rof_max_iter, pr->rof_max_backtrack, nullptr, 0, 0, b.sst,
+                                        b.rec, b.rec_cap, level, 0, true, s)))
+            return st;
+        if ((st = flush_small(b, s, sink, &pos))) return st;
+    } else if ((st = rof_loop(L, pr, pr->step, b, s, sink, level, 0, &pos))) {
+        return st;
+    }
     CBCT_HIP(hipMemcpyAsync(d_u, b.u, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
     if (stats) stats->replay_used = pos;
     return CBCT_OK;

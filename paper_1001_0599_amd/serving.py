@@ -77,6 +77,12 @@ class Server:
         return dict(in_use=a.value, peak_in_use=b.value, running=c.value, peak_running=d.value, queued=e.value,
                     completed=f.value)
 
+    def batch_stats(self):
+        """(batched launches, request items they carried) of the batch engine."""
+        a, b = C.c_uint64(), C.c_uint64()
+        check(lib().cbct_server_batch_stats(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def close(self):
         if getattr(self, "_h", None):
             lib().cbct_server_destroy(self._h)

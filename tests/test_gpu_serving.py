@@ -44,11 +44,15 @@ def test_mixed_requests_equal_solo_results():
         tickets.append(srv.submit(g, yin, o, lam=0.05, iters=(10,)))
     srv.wait_all()
     st = srv.stats()
-    assert st["completed"] == len(reqs) and st["peak_in_use"] <= 4e9
+    # peak_in_use: the device bytes the server obtained (pool blocks and plan tables)
+    assert st["completed"] == len(reqs) and 0 < st["peak_in_use"] <= 4e9
     for t, o, s in zip(tickets, outs, solo):
         done, status, lat = srv.poll(t)
         assert done and status == 0 and lat > 0
         assert torch.equal(o, s)
+    # the engine's launches carried several requests' work-groups
+    launches, items = srv.batch_stats()
+    assert launches > 0 and items > launches, (launches, items)
     srv.close()
 
 
@@ -91,4 +95,35 @@ def test_budget_serialises_when_tight():
     srv.wait_all()
     st = srv.stats()
     assert st["peak_in_use"] <= 1.05 * one
+    srv.close()
+
+
+def test_device_bytes_stay_within_budget():
+    """Real device bytes (pooled blocks, idle ones included, and cached plan tables) never exceed
+    the budget, also when many distinct geometries pass through (idle blocks and unused plans are
+    given back), and a hipMemGetInfo drop taken while the server runs stays within it."""
+    from paper_1001_0599_amd.serving import Server
+    announce("serving: device bytes under a tight budget, 6 geometries")
+    reqs = _requests()
+    srv = Server(budget_bytes=1e12, max_slots=1)
+    srv.submit(reqs[3][0], reqs[3][1], torch.empty(reqs[3][0].vol_shape, device="cuda"), iters=(1,))
+    srv.wait_all()
+    biggest = srv.stats()["peak_in_use"]
+    srv.close()
+    budget = int(1.6 * biggest)
+    srv = Server(budget_bytes=budget, max_slots=4)
+    outs = [torch.empty(g.vol_shape, device="cuda") for g, _ in reqs]
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    for (g, y), o in zip(reqs, outs):
+        srv.submit(g, y, o, iters=(2,))
+    low = free1
+    while srv.stats()["completed"] < len(reqs):
+        low = min(low, torch.cuda.mem_get_info()[0])
+    srv.wait_all()
+    st = srv.stats()
+    assert st["peak_in_use"] <= budget, (st, budget)
+    # allocation granularity aside (the runtime carves small tables out of larger chunks), what
+    # the device lost is what the server holds
+    assert free1 - low <= budget + (128 << 20), (free1 - low, budget)
     srv.close()

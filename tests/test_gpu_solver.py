@@ -331,3 +331,51 @@ def test_full_size_solve_properties():
     for lvl in range(2):
         e = en[lvl * 5:(lvl + 1) * 5]
         assert np.all(np.diff(e) <= 1e-6 * e[:-1]), e
+
+
+GOLDEN_FULL = "tests/golden/full_solve_512x512x64_40views.npz"
+
+
+def test_full_size_solve_matches_stored_oracle():
+    """The benchmark workload end to end: Algorithm A1 with the two-level cascade of Section II.C.3,
+    [20, 20] outer iterations at 512x512x64 / 40 views / 512x384, against the FP64 oracle's solve of
+    the same seeded inputs (stored by tests/golden/make_full_solve_golden.py, which calls only the
+    oracle): the ROF decision trace exactly (replaying the oracle's decisions only on an FP32 tie,
+    margin < 1e-6 of E_0), the energy trace within rel-L2 1e-4, t per level within 1e-5, and 20000
+    seeded voxels within rel-L2 1e-3."""
+    import hashlib
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), GOLDEN_FULL)
+    if not os.path.exists(path):
+        pytest.skip("stored oracle solve not generated (tests/golden/make_full_solve_golden.py)")
+    ref = np.load(path, allow_pickle=False)
+    cfg = S.CONFIGS["wide512x512x64"]
+    g = cfg["geometry"]
+    announce("reconstruct 512x512x64, 40 views, [20, 20], against the stored oracle solve")
+    ph = S.make_phantom(g, cfg["seeds"][0])
+    Yd = np.ascontiguousarray(S.poisson_log(S.analytic_projections(g, ph), cfg["I0"], cfg["seeds"][1]),
+                              dtype=np.float64)
+    assert hashlib.sha256(Yd.tobytes()).hexdigest() == str(ref["y_sha256"]), "inputs differ from the stored solve"
+    trace, rof_e = ref["trace"], ref["rof_e"]
+    plan = _plan(g, cfg["levels"])
+    f, st = plan.reconstruct(to_gpu(Yd), lam=cfg["lam"], iters=cfg["iters"], stats=True)
+
+    class R:  # the oracle result as _margins reads it
+        pass
+    res = R()
+    res.trace, res.rof_e, res.t_used = trace, rof_e, list(ref["t_used"])
+    q = _first_divergence(st["trace"], trace)
+    if q is not None:
+        margins = _margins(res, q)
+        assert margins and min(margins) < TIE_MARGIN, ("decision diverged with a large margin", q, margins)
+        f, st = plan.reconstruct(to_gpu(Yd), lam=cfg["lam"], iters=cfg["iters"], stats=True,
+                                 replay=replay_records(trace))
+        assert [tuple(r) for r in st["trace"]] == [tuple(r) for r in trace]
+        REPLAYS.append((g.vol_shape, tuple(cfg["iters"]), q, len(trace), min(margins)))
+        print("[replay] full size: first divergence at record %d of %d" % (q, len(trace)), flush=True)
+    for l in range(cfg["levels"]):
+        assert abs(st["t_used"][l] - ref["t_used"][l]) / ref["t_used"][l] < 1e-5
+    assert rel_l2(st["energy"], ref["energy"]) < 1e-4
+    got = to_np(f).ravel()[ref["vox"]]
+    err = np.linalg.norm(got - ref["f_vox"]) / (np.linalg.norm(ref["f_vox"]) + 1e-300)
+    assert err < 1e-3, err
