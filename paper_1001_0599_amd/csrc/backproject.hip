@@ -32,12 +32,12 @@ template <bool PREWEIGHTED>
 __global__ void __launch_bounds__(256)
     k_adj_profiles(const float *__restrict__ proj, const ColParams *__restrict__ cols,
                    const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, bool gb_lds,
-                   float *__restrict__ Z) {
+                   float *__restrict__ Z, int view0) {
     extern __shared__ double2 ab[];  // [nv + 1]: (A, B), then [max nk] per-sample constants
     __shared__ double wtot[4][2];
     // adjacent columns share the cache lines of their projection rows: keep them on one XCD
     const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int i = w % nu, view = w / nu;
+    const int i = w % nu, view = view0 + w / nu;  // the launch covers views view0 .. view0 + gridDim.y - 1
     const long col = (long)view * nu + i;
     const ColParams cp = cols[col];
     const ZIndex zi = zix[col];
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256)
     k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
                         const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
                         int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
-                        float *__restrict__ part) {
+                        float *__restrict__ part, int grp0) {
     constexpr int GS_Q = GS_TZ / 4;                 // float4 slots per profile row
     constexpr int GS_QS = GS_TZ == 64 ? 4 : 3;      // log2(GS_Q)
     constexpr int GS_PITCH = GS_Q + 1;              // one pad slot per staged row against bank conflicts
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(256)
 
     int tx, ty, tzg;
     tile_of(tx, ty, tzg);
-    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = tzg / nzt;
+    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = grp0 + tzg / nzt;  // groups grp0 .. of this launch
     const int v_begin = grp * vper, v_end = min(A.nviews, v_begin + vper);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY, c0 = tz * GS_TZ;
@@ -526,22 +526,58 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
     size_t lds = sizeof(double2) * (L.nv + 1 + L.zk_max);
     const bool gb_lds = lds <= 64 * 1024;
     if (!gb_lds) lds = sizeof(double2) * (L.nv + 1);
-    dim3 g1(L.nu, L.nviews);
-    if (preweighted)
-        hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
-                           (float)L.pv, gb_lds, Zws);
-    else
-        hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
-                           (float)L.pv, gb_lds, Zws);
-    LAUNCH_CHECK("k_adj_profiles");
+    // profiles of views [v0, v1) on stream st
+    const auto profiles = [&](int v0, int v1, hipStream_t st) -> cbct_status {
+        if (v1 <= v0) return CBCT_OK;
+        dim3 g1(L.nu, v1 - v0);
+        if (preweighted)
+            hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, st, proj, L.d_cols, L.d_zix, L.nu, L.nv,
+                               L.nz, (float)L.pv, gb_lds, Zws, v0);
+        else
+            hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, st, proj, L.d_cols, L.d_zix, L.nu, L.nv,
+                               L.nz, (float)L.pv, gb_lds, Zws, v0);
+        LAUNCH_CHECK("k_adj_profiles");
+        return CBCT_OK;
+    };
     const int nz = L.nz;
     const int tzs = cbct_adj_staged_tz(nz);  // 32 or 0
+    cbct_status st;
+    if (tzs && L.adj_vsplit > 1 && L.pipe) {
+        // pipelined: profiles of group g + 1 (this stream) overlap the gather of group g (helper
+        // stream); the view-group sum waits for every gather
+        const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
+        float *part = Zws + L.adj_part_off;
+        AdjPipe &P = *L.pipe;
+        std::lock_guard<std::mutex> lk(P.mu);
+        hipEvent_t e_edge = P.ev[vg];
+        // the helper stream starts after the caller's earlier work (the profile workspace and the
+        // partial volumes may still be in use by it)
+        CBCT_HIP(hipEventRecord(e_edge, s));
+        CBCT_HIP(hipStreamWaitEvent(P.aux, e_edge, 0));
+        dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, nz / tzs);
+        for (int g = 0; g < vg; g++) {
+            if ((st = profiles(g * vper, std::min(L.nviews, (g + 1) * vper), s))) return st;
+            CBCT_HIP(hipEventRecord(P.ev[g], s));
+            CBCT_HIP(hipStreamWaitEvent(P.aux, P.ev[g], 0));
+            hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, P.aux, Zws,
+                               L.d_zix, L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part, g);
+            LAUNCH_CHECK("k_adj_gather_staged");
+        }
+        CBCT_HIP(hipEventRecord(e_edge, P.aux));
+        CBCT_HIP(hipStreamWaitEvent(s, e_edge, 0));
+        const long n = L.nvox();
+        const int nb = (int)std::min<long>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out, out2);
+        LAUNCH_CHECK("k_adj_combine");
+        return CBCT_OK;
+    }
+    if ((st = profiles(0, L.nviews, s))) return st;
     if (tzs) {
         const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
         float *part = Zws + L.adj_part_off;
         dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / tzs) * vg);
         hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix,
-                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part);
+                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part, 0);
         LAUNCH_CHECK("k_adj_gather_staged");
         if (vg > 1) {
             const long n = L.nvox();
@@ -560,7 +596,6 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
     else if (nz % 16 == 0) tz = 16;
     else if (nz % 8 == 0) tz = 8;
     else tz = nz > 32 ? 64 : nz > 16 ? 32 : nz > 8 ? 16 : 8;  // partial last tile, scalar loads
-    cbct_status st;
     switch (tz) {
         case 64: st = launch_gather<64>(L, Zws, fbase, kappa, out, s); break;
         case 32: st = launch_gather<32>(L, Zws, fbase, kappa, out, s); break;
