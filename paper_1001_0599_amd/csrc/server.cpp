@@ -202,6 +202,26 @@ namespace {
 
 void note_device(cbct_server *s) { s->peak_device = std::max(s->peak_device, s->owned + s->plan_total); }
 
+// (mu held) give back the least recently used cached plans that no running request uses until
+// `fits()` holds or none is left
+// (`keep`: a plan the caller is about to use, never evicted)
+template <class F>
+void evict_plans(cbct_server *s, F fits, const std::string *keep = nullptr) {
+    while (!fits()) {
+        auto victim = s->plans.end();
+        for (auto q = s->plans.begin(); q != s->plans.end(); ++q)
+            if (q->second.users == 0 && q->second.plan && !(keep && q->first == *keep) &&
+                (victim == s->plans.end() || q->second.last_use < victim->second.last_use))
+                victim = q;
+        if (victim == s->plans.end()) return;
+        DeviceGuard dg(s->ctx.device);
+        cbct_plan_destroy(victim->second.plan);
+        s->plan_total -= victim->second.bytes;
+        s->held -= victim->second.bytes;
+        s->plans.erase(victim);
+    }
+}
+
 // (mu held) a block of exactly size class n: an idle one, or a new one; idle blocks, then unused
 // cached plans, are released while a new allocation would take the server past its budget
 void *pool_get(cbct_server *s, size_t n) {
@@ -218,17 +238,7 @@ void *pool_get(cbct_server *s, size_t n) {
         s->owned -= big->first;
         s->free_blocks.erase(big);
     }
-    while (s->owned + s->plan_total + n > s->budget) {
-        auto victim = s->plans.end();
-        for (auto q = s->plans.begin(); q != s->plans.end(); ++q)
-            if (q->second.users == 0 && (victim == s->plans.end() || q->second.last_use < victim->second.last_use))
-                victim = q;
-        if (victim == s->plans.end()) break;
-        cbct_plan_destroy(victim->second.plan);
-        s->plan_total -= victim->second.bytes;
-        s->held -= victim->second.bytes;
-        s->plans.erase(victim);
-    }
+    evict_plans(s, [&] { return s->owned + s->plan_total + n <= s->budget; });
     void *p = nullptr;
     if (hipMalloc(&p, n) != hipSuccess) {
         (void)hipGetLastError();
@@ -280,6 +290,12 @@ cbct_status acquire_plan(cbct_server *s, Request *r) {
     PlanEntry &e = s->plans[r->key];
     e.plan = p;
     e.bytes = r->plan_bytes;
+    if (!e.bytes) {
+        // charged nothing at submit (the plan was cached then and has been evicted since): charge
+        // its tables now
+        e.bytes = estimate_plan_bytes(r->g, r->levels);
+        s->held += e.bytes;
+    }
     e.users = 1;
     e.last_use = clk::now();
     s->plan_total += e.bytes;
@@ -652,7 +668,10 @@ void engine_main(cbct_server *s, int cls) {
 void admit(cbct_server *s) {
     while (!s->queue.empty() && !s->stop) {
         Request *h = s->queue.front();
-        if (s->running >= s->max_slots || s->held + h->bytes > s->budget) break;
+        if (s->running >= s->max_slots) break;
+        // cached plans nobody uses make room for the head (its own plan is charged to it while new)
+        if (!s->simulated) evict_plans(s, [&] { return s->held + h->bytes <= s->budget; }, &h->key);
+        if (s->held + h->bytes > s->budget) break;
         if (s->simulated) {
             // no device work: the request holds its slot and bytes for its service time
         } else if (!h->batchable) {
