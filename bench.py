@@ -30,7 +30,7 @@ def log(msg):
 # TCC_MISS).  The record names the sources it was measured on; it is reported only while they are
 # unchanged.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "adjoint_traffic_512x512x64_40views.txt")
-TRAFFIC_SOURCES = ["backproject.hip", "cbct_internal.h", "plan.cpp"]
+TRAFFIC_SOURCES = ["backproject.hip", "adj_profiles.h", "cbct_internal.h", "plan.cpp"]
 
 
 def sources_digest(names):
@@ -241,6 +241,9 @@ def kernels_only():
     plan.adjoint_siddon(y, out=vol, workspace=sws)
     del sws
     plan.tv_prox(fv, 0.05, 1e-3)
+    # one outer iteration of the solver: the residual projector fused with the adjoint's profile
+    # pass, and the gather alone in Step 1
+    plan.reconstruct(y, lam=0.05, iters=[1])
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": 2 * 4 * a.numel()}))
 
@@ -292,7 +295,8 @@ def counter_summary(fetch_dir, write_dir, hit_dir):
     def pick(tab, prefix, cn):
         # the mean over the kernel's dispatches; for the copy, its largest dispatch (the 256 MiB
         # calibration copy, not the small copies around it)
-        vals = [v for (k, c), v in tab.items() if c == cn and k.startswith(prefix)]
+        vals = [v for (k, c), v in tab.items()
+                if c == cn and (k == prefix or k.startswith(prefix + "<") or k.startswith(prefix + "("))]
         if len(vals) != 1:
             return None
         return max(vals[0]) if prefix == COUNTER_KERNELS[0][1] else sum(vals[0]) / len(vals[0])
@@ -341,6 +345,65 @@ def counter_summary(fetch_dir, write_dir, hit_dir):
     print("\n".join(lines))
 
 
+SQ_KERNELS = ["k_forward_runs", "k_adj_profiles", "k_adj_gather_staged", "k_adj_combine",
+              "k_backproject_eq6", "k_siddon_forward_runs", "k_sid_profiles", "k_sid_gather_pieces", "k_tv_grad",
+              "k_tv_trial", "k_sum_rows"]
+
+
+def sq_summary(d):
+    """Instruction-mix record of the hot kernels from one rocprofv3 run of --kernels-only with the
+    SQ counters (wave-level instruction counts, LDS bank-conflict cycles, busy and wave cycles) and
+    the kernel durations of the same run."""
+    import glob
+    import re
+    import sqlite3
+    from collections import defaultdict
+
+    names = ["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+             "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_WAVES"]
+    tab = {n: read_counters(d, {n}) for n in names}
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    con = sqlite3.connect(dbs[0])
+    dur = defaultdict(list)
+    for name, du in con.execute("select name, duration from kernels"):
+        k = re.sub(r"\(.*", "", name.replace("void ", "").replace("(anonymous namespace)::", ""))
+        dur[k].append(du)
+
+    def pick(t, pre):
+        vals = [v for (k, c), v in t.items() if k == pre or k.startswith(pre + "<")]
+        return sum(vals[0]) / len(vals[0]) if len(vals) == 1 else None
+
+    def dpick(pre):
+        v = [x for k, xs in dur.items() if k == pre or k.startswith(pre + "<") for x in xs]
+        return sum(v) / len(v) if v else None
+
+    peak_issue = 256 * 2.4e9  # VALU wave-instructions per second: 256 CUs, one per clock each
+    lines = [
+        "Instruction mix of the hot kernels, 512x512x64 voxels, 40 views, 512x384 detector (MI355X, gfx950).",
+        "One rocprofv3 run of the same program, from the repository root:",
+        "  cd /tmp && export TMPDIR=/tmp",
+        "  rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+        "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_WAVES --kernel-trace -d <dir> -o run -- python3 <repo>/bench.py "
+        "--kernels-only",
+        "  python3 bench.py --sq-summary <dir>",
+        "Counts are per dispatch (means over the kernel's dispatches), wave-level instructions.  'VALU at peak' is",
+        "SQ_INSTS_VALU / (256 CUs x 2.4 GHz x 1 wave-instruction per CU per clock): the time the kernel would take",
+        "if VALU issue were its only limit; 'VALU share' is that over the kernel's duration in this run.",
+        "",
+        "  %-26s %12s %10s %12s %11s %9s %10s %9s" % ("kernel", "VALU instr", "LDS instr", "bank confl",
+                                                    "confl/LDS", "dur us", "VALU@pk us", "VALU shr"),
+    ]
+    for k in SQ_KERNELS:
+        va, ld, bc = pick(tab["SQ_INSTS_VALU"], k), pick(tab["SQ_INSTS_LDS"], k), pick(tab["SQ_LDS_BANK_CONFLICT"], k)
+        du = dpick(k)
+        if va is None or du is None:
+            continue
+        t_pk = va / peak_issue * 1e6
+        lines.append("  %-26s %12.4g %10.4g %12.4g %11.2f %9.1f %10.1f %8.0f%%" % (
+            k, va, ld or 0, bc or 0, (bc or 0) / ld if ld else 0.0, du / 1e3, t_pk, 100 * t_pk / (du / 1e3)))
+    print("\n".join(lines))
+
+
 def trace_summary(d, top=40):
     """Per kernel and launch grid: calls, total / mean / min / max duration, share, VGPRs and LDS,
     from the kernel trace in a rocprofv3 output directory (its SQLite database)."""
@@ -385,12 +448,16 @@ def main():
     ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "HIT_DIR"),
                     help="print the traffic / L2 hit-rate record from three counter runs of --kernels-only")
     ap.add_argument("--trace-summary", metavar="DIR", help="per-kernel table of a rocprofv3 kernel-trace run")
+    ap.add_argument("--sq-summary", metavar="DIR", help="instruction-mix record from a rocprofv3 SQ-counter run")
     args = ap.parse_args()
     if args.counter_summary:
         counter_summary(*args.counter_summary)
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary)
         return
     if args.kernels_only:
         kernels_only()

@@ -23,6 +23,7 @@
 #include <cfloat>
 
 #include "cbct_internal.h"
+#include "adj_profiles.h"
 
 namespace {
 
@@ -32,123 +33,12 @@ template <bool PREWEIGHTED>
 __global__ void __launch_bounds__(256)
     k_adj_profiles(const float *__restrict__ proj, const ColParams *__restrict__ cols,
                    const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, bool gb_lds,
-                   float *__restrict__ Z, int view0) {
-    extern __shared__ double2 ab[];  // [nv + 1]: (A, B), then [max nk] per-sample constants
-    __shared__ double wtot[4][2];
+                   float *__restrict__ Z) {
     // adjacent columns share the cache lines of their projection rows: keep them on one XCD
     const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int i = w % nu, view = view0 + w / nu;  // the launch covers views view0 .. view0 + gridDim.y - 1
+    const int i = w % nu, view = w / nu;
     const long col = (long)view * nu + i;
-    const ColParams cp = cols[col];
-    const ZIndex zi = zix[col];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float iv = 0.5f * (float)(nv - 1);
-    // prefix sums: rows in chunks of 256, each chunk scanned by the block (wave scans + wave totals)
-    double carry_a = 0.0, carry_b = 0.0;
-    if (tid == 0) ab[0] = make_double2(0.0, 0.0);
-    for (int j0 = 0; j0 < nv; j0 += 256) {
-        const int j = j0 + tid;
-        double wa = 0.0, wb = 0.0;
-        if (j < nv) {
-            float w = proj[((long)view * nv + j) * nu + i];
-            const float q = (float)j - iv;
-            if (!PREWEIGHTED) {
-                const float v = q * pv;
-                w *= cp.wsc * sqrtf(fmaf(v, v, cp.r2));
-            }
-            wa = (double)w;
-            wb = (double)w * (double)q;
-        }
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double ta = __shfl_up(wa, o), tb = __shfl_up(wb, o);
-            if (lane >= o) {
-                wa += ta;
-                wb += tb;
-            }
-        }
-        if (lane == 63) {
-            wtot[wave][0] = wa;
-            wtot[wave][1] = wb;
-        }
-        __syncthreads();
-        double oa = carry_a, ob = carry_b;
-        for (int w = 0; w < wave; w++) {
-            oa += wtot[w][0];
-            ob += wtot[w][1];
-        }
-        if (j < nv) ab[j + 1] = make_double2(oa + wa, ob + wb);
-        for (int w = 0; w < 4; w++) {
-            carry_a += wtot[w][0];
-            carry_b += wtot[w][1];
-        }
-        __syncthreads();
-    }
-    // profiles: items (sample, CG consecutive cells), cells fastest.  J(x) = ceil(x / gamma + iv -
-    // beta / gamma) is monotone in x, so the row ranges [J(c-1), J(c)) and [J(c), J(c+1)) never
-    // overlap; CG + 2 boundaries serve the item's CG cells.
-#ifndef CBCT_PROF_CG
-#define CBCT_PROF_CG 4
-#endif
-    constexpr int CG = CBCT_PROF_CG;
-    const double beta = 0.5 * (double)(nz - 1);
-    const int nq = (nz + CG - 1) / CG;
-    const bool vec = (nz & 3) == 0;
-    float *zc = Z + zi.off;
-    // per sample: 1 / gamma and iv - beta / gamma, once (an FP64 division is a long sequence),
-    // when the column's samples fit in LDS
-    double2 *gb = ab + (nv + 1);
-    if (gb_lds) {
-        for (int kk = tid; kk < zi.nk; kk += blockDim.x) {
-            const double ig = 1.0 / (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
-            gb[kk] = make_double2(ig, (double)iv - beta * ig);
-        }
-        __syncthreads();
-    }
-    // items it = tid + m * blockDim: (kk, cq) advance by (dkk, dcq) with one carry
-    const int dkk = (int)blockDim.x / nq, dcq = (int)blockDim.x - dkk * nq;
-    int kk = tid / nq, cq = tid - kk * nq;
-    for (; kk < zi.nk; kk += dkk, cq += dcq) {
-        if (cq >= nq) {
-            cq -= nq;
-            if (++kk >= zi.nk) break;
-        }
-        const int cg0 = cq * CG;
-        const double gamma = (double)fmaf((float)(zi.k0 + kk), cp.dg, cp.g0);
-        double ig, base;
-        if (gb_lds) {
-            const double2 gbk = gb[kk];
-            ig = gbk.x;
-            base = gbk.y;
-        } else {
-            ig = 1.0 / gamma;
-            base = (double)iv - beta * ig;
-        }
-        double2 pr[CG + 2];
-#pragma unroll
-        for (int q = 0; q < CG + 2; q++) {
-            const double r = ceil(fma((double)(cg0 - 1 + q), ig, base));
-            pr[q] = ab[(int)fmin(fmax(r, 0.0), (double)nv)];
-        }
-        float o[CG];
-#pragma unroll
-        for (int q = 0; q < CG; q++) {
-            const double c = (double)(cg0 + q);
-            const double dal = pr[q + 1].x - pr[q].x, dbl = pr[q + 1].y - pr[q].y;          // s in [c-1, c)
-            const double dah = pr[q + 2].x - pr[q + 1].x, dbh = pr[q + 2].y - pr[q + 1].y;  // s in [c, c+1)
-            o[q] = (float)(gamma * (dbl - dbh) + (beta - c + 1.0) * dal + (c + 1.0 - beta) * dah);
-        }
-        float *dst = zc + (long)kk * nz + cg0;
-        if (vec && (CG & 3) == 0 && cg0 + CG <= nz) {
-#pragma unroll
-            for (int q = 0; q < CG / 4; q++)
-                *reinterpret_cast<float4 *>(dst + 4 * q) = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < CG; q++)
-                if (cg0 + q < nz) dst[q] = o[q];
-        }
-    }
+    column_profiles<PREWEIGHTED>(proj + (long)view * nv * nu + i, nu, cols[col], zix[col], nv, nz, pv, gb_lds, Z);
 }
 
 // ---------------------------------------------------------------------------- pass 2
@@ -311,18 +201,18 @@ __global__ void __launch_bounds__(256)
     k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
                         const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
                         int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
-                        float *__restrict__ part, int grp0) {
+                        float *__restrict__ part) {
     constexpr int GS_Q = GS_TZ / 4;                 // float4 slots per profile row
     constexpr int GS_QS = GS_TZ == 64 ? 4 : 3;      // log2(GS_Q)
     constexpr int GS_PITCH = GS_Q + 1;              // one pad slot per staged row against bank conflicts
     __shared__ float4 zs[(GS_ROWS + 1) * GS_PITCH];  // + one spill row for the staging's idle slots
     __shared__ GsCol ci[GS_CC];
     __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
-    __shared__ long rowsrc[GS_ROWS];  // profile offset of each staged row
+    __shared__ int rowsrc[GS_ROWS];  // profile offset of each staged row, in float4 units
 
     int tx, ty, tzg;
     tile_of(tx, ty, tzg);
-    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = grp0 + tzg / nzt;  // groups grp0 .. of this launch
+    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = tzg / nzt;
     const int v_begin = grp * vper, v_end = min(A.nviews, v_begin + vper);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY, c0 = tz * GS_TZ;
@@ -398,33 +288,37 @@ __global__ void __launch_bounds__(256)
                 if (tid < nc) {
                     const int r_a = max(cnt[tid], R0), r_b = min(cnt[tid + 1], R0 + nrows);
                     const long z0 = ci[tid].zrow - (long)cnt[tid] * A.nz;
-                    for (int r = r_a; r < r_b; r++) rowsrc[r - R0] = z0 + (long)r * A.nz;
+                    for (int r = r_a; r < r_b; r++) rowsrc[r - R0] = (int)((z0 + (long)r * A.nz) >> 2);
                 }
                 __syncthreads();
                 // stage the rows: 8 lanes per 128-byte row; every load of the batch is issued
                 // before the first LDS store, so the batch pays one memory latency
                 {
+                    // slot j of this thread holds float4 `sl` of batch row row0 + RSTEP j (the
+                    // addresses are per-thread constants plus immediates)
                     constexpr int PER = (GS_ROWS * GS_Q + 255) / 256;
-                    const int items = nrows * GS_Q;  // > 0
-                    float4 v[PER];
+                    constexpr int RSTEP = 256 >> GS_QS;
+                    static_assert(PER <= 10, "one asm statement consumes the batch's loads");
+                    const int row0 = tid >> GS_QS, sl = tid & (GS_Q - 1);
+                    const float4 *Z4 = reinterpret_cast<const float4 *>(Z);
+                    float4 v[10];
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
-                        // items past the batch load its last row again (no branch between the loads)
-                        const int it = min(tid + 256 * j, items - 1);
-                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1)));
+                        // slots past the batch load its last row again (no branch between the loads)
+                        const int rr = min(row0 + RSTEP * j, nrows - 1);
+                        v[j] = Z4[(unsigned)rowsrc[rr] + (unsigned)sl];
                     }
-                    // all loads in flight before the first store: an empty asm statement consumes
-                    // every loaded word here, so the compiler cannot sink (or split) each load
-                    // down to its store; idle slots store into the spill row
-                    float dep = 0.0f;
 #pragma unroll
-                    for (int j = 0; j < PER; j++) dep += (v[j].x + v[j].y) + (v[j].z + v[j].w);
-                    asm volatile("" ::"v"(dep));
+                    for (int j = PER; j < 10; j++) v[j] = v[0];
+                    // every load of the batch is in flight before the first store: one empty asm
+                    // statement consumes a word of each (a load is one whole float4), so none can be
+                    // sunk down to its store; idle slots store into the spill row
+                    asm volatile("" ::"v"(v[0].x), "v"(v[1].x), "v"(v[2].x), "v"(v[3].x), "v"(v[4].x), "v"(v[5].x),
+                                 "v"(v[6].x), "v"(v[7].x), "v"(v[8].x), "v"(v[9].x));
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
-                        const int it = tid + 256 * j;
-                        const int r = it < items ? (it >> GS_QS) : GS_ROWS;
-                        zs[r * GS_PITCH + (it & (GS_Q - 1))] = v[j];
+                        const int r = row0 + RSTEP * j;
+                        zs[(r < nrows ? r : GS_ROWS) * GS_PITCH + sl] = v[j];
                     }
                 }
                 __syncthreads();
@@ -526,58 +420,23 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
     size_t lds = sizeof(double2) * (L.nv + 1 + L.zk_max);
     const bool gb_lds = lds <= 64 * 1024;
     if (!gb_lds) lds = sizeof(double2) * (L.nv + 1);
-    // profiles of views [v0, v1) on stream st
-    const auto profiles = [&](int v0, int v1, hipStream_t st) -> cbct_status {
-        if (v1 <= v0) return CBCT_OK;
-        dim3 g1(L.nu, v1 - v0);
-        if (preweighted)
-            hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, st, proj, L.d_cols, L.d_zix, L.nu, L.nv,
-                               L.nz, (float)L.pv, gb_lds, Zws, v0);
-        else
-            hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, st, proj, L.d_cols, L.d_zix, L.nu, L.nv,
-                               L.nz, (float)L.pv, gb_lds, Zws, v0);
-        LAUNCH_CHECK("k_adj_profiles");
-        return CBCT_OK;
-    };
+    dim3 g1(L.nu, L.nviews);
+    if (preweighted)
+        hipLaunchKernelGGL((k_adj_profiles<true>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
+                           (float)L.pv, gb_lds, Zws);
+    else
+        hipLaunchKernelGGL((k_adj_profiles<false>), g1, dim3(256), lds, s, proj, L.d_cols, L.d_zix, L.nu, L.nv, L.nz,
+                           (float)L.pv, gb_lds, Zws);
+    LAUNCH_CHECK("k_adj_profiles");
     const int nz = L.nz;
     const int tzs = cbct_adj_staged_tz(nz);  // 32 or 0
     cbct_status st;
-    if (tzs && L.adj_vsplit > 1 && L.pipe) {
-        // pipelined: profiles of group g + 1 (this stream) overlap the gather of group g (helper
-        // stream); the view-group sum waits for every gather
-        const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
-        float *part = Zws + L.adj_part_off;
-        AdjPipe &P = *L.pipe;
-        std::lock_guard<std::mutex> lk(P.mu);
-        hipEvent_t e_edge = P.ev[vg];
-        // the helper stream starts after the caller's earlier work (the profile workspace and the
-        // partial volumes may still be in use by it)
-        CBCT_HIP(hipEventRecord(e_edge, s));
-        CBCT_HIP(hipStreamWaitEvent(P.aux, e_edge, 0));
-        dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, nz / tzs);
-        for (int g = 0; g < vg; g++) {
-            if ((st = profiles(g * vper, std::min(L.nviews, (g + 1) * vper), s))) return st;
-            CBCT_HIP(hipEventRecord(P.ev[g], s));
-            CBCT_HIP(hipStreamWaitEvent(P.aux, P.ev[g], 0));
-            hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, P.aux, Zws,
-                               L.d_zix, L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part, g);
-            LAUNCH_CHECK("k_adj_gather_staged");
-        }
-        CBCT_HIP(hipEventRecord(e_edge, P.aux));
-        CBCT_HIP(hipStreamWaitEvent(s, e_edge, 0));
-        const long n = L.nvox();
-        const int nb = (int)std::min<long>((n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out, out2);
-        LAUNCH_CHECK("k_adj_combine");
-        return CBCT_OK;
-    }
-    if ((st = profiles(0, L.nviews, s))) return st;
     if (tzs) {
         const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
         float *part = Zws + L.adj_part_off;
         dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / tzs) * vg);
         hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix,
-                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part, 0);
+                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part);
         LAUNCH_CHECK("k_adj_gather_staged");
         if (vg > 1) {
             const long n = L.nvox();

@@ -79,20 +79,6 @@ struct ZIndex {
 };
 static_assert(sizeof(ZIndex) == 16, "ZIndex layout");
 
-// Overlap of the adjoint's two passes across view groups: the z profiles of group g + 1 are
-// written on the caller's stream while group g's gather runs on a helper stream of the plan (the
-// profile pass is bound by HBM writes, the gather by reads and LDS/VALU work).  The lock keeps the
-// event records and waits of concurrent calls on one plan in order.
-struct AdjPipe {
-    hipStream_t aux = nullptr;
-    std::vector<hipEvent_t> ev;  // one per view group, and one for the start and the end
-    std::mutex mu;
-    ~AdjPipe() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-        if (aux) (void)hipStreamDestroy(aux);
-    }
-};
-
 struct Level {
     int nx, ny, nz, nu, nv, nviews;
     double hx, hy, hz, pu, pv, sad, sdd, dtau;
@@ -109,7 +95,6 @@ struct Level {
     int adj_vsplit = 1;           // view groups of the staged gather
     long adj_part_off = 0;        // float offset of the view-group partial volumes
     ZIndex *d_zix = nullptr;      // [nviews][nu]
-    std::shared_ptr<AdjPipe> pipe;  // profiles / gather overlap (staged gather with view groups)
     double schur_t = 0.0;         // cached Schur-bound step of the trilinear pair (0: not computed yet)
     double schur_t_siddon = 0.0;  // the same for the Siddon pair
     // device tables

@@ -163,15 +163,14 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
         zoff += ((long)nk * L.nz + 31) & ~31L;  // column blocks start on 128-byte lines
     }
     L.adj_vsplit = cbct_adj_vsplit(L.nx, L.ny, L.nz, L.nviews);
-    if (const char *ev = std::getenv("CBCT_ADJ_GROUPS")) {  // tuning override of the view groups
-        const int gset = std::atoi(ev);
-        if (gset >= 1 && gset <= 16 && cbct_adj_staged_tz(L.nz)) L.adj_vsplit = std::min(gset, L.nviews);
-    }
     if (L.adj_vsplit > 1) {
         L.adj_part_off = (zoff + 63) & ~63L;
         zoff = L.adj_part_off + (long)L.adj_vsplit * L.nvox();
     }
     L.z_floats = std::max(zoff, 4L);
+    if (cbct_adj_staged_tz(L.nz) && L.z_floats / 4 > 0x7fffffffL)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "level %d: adjoint profiles of %.1f GB exceed the gather's 32 GB "
+                              "addressing", l, 4e-9 * (double)L.z_floats);
     AdjArgs &A = L.adj;
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
     A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
@@ -196,13 +195,6 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     CBCT_HIP(hipMemcpy(L.d_sid, sid.data(), sizeof(SidCol) * sid.size(), hipMemcpyHostToDevice));
     CBCT_HIP(hipMalloc((void **)&L.d_zix, sizeof(ZIndex) * zix.size()));
     CBCT_HIP(hipMemcpy(L.d_zix, zix.data(), sizeof(ZIndex) * zix.size(), hipMemcpyHostToDevice));
-    if (L.adj_vsplit > 1) {
-        auto pipe = std::make_shared<AdjPipe>();
-        CBCT_HIP(hipStreamCreateWithFlags(&pipe->aux, hipStreamNonBlocking));
-        pipe->ev.resize(L.adj_vsplit + 1, nullptr);
-        for (auto &e : pipe->ev) CBCT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        L.pipe = pipe;
-    }
     return CBCT_OK;
 }
 
@@ -286,7 +278,6 @@ extern "C" void cbct_plan_destroy(cbct_plan *p) {
     if (!p) return;
     DeviceGuard dg(p->device);
     for (auto &L : p->lv) {
-        L.pipe.reset();
         if (L.d_cols) hipFree(L.d_cols);
         if (L.d_views) hipFree(L.d_views);
         if (L.d_zix) hipFree(L.d_zix);

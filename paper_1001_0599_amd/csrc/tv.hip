@@ -239,27 +239,43 @@ __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, c
 constexpr int SUM_MAXW = 3 + 2 * CBCT_TRIALS;
 __device__ __forceinline__ void sum_rows_body(const double *__restrict__ part, int nb, int width,
                                               double *__restrict__ out) {
-    __shared__ double sh[SUM_MAXW][256];
-    const int per = (nb + blockDim.x - 1) / blockDim.x;
-    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    // thread t sums rows t, t + 256, ... (coalesced loads, several in flight), each wave folds its
+    // 64 lanes with a fixed butterfly (lane 0's result is kept), and the wave totals are added in
+    // wave order: a fixed order, so the sums are bitwise reproducible
+    __shared__ double sh[4][SUM_MAXW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double s[SUM_MAXW];
 #pragma unroll
     for (int j = 0; j < SUM_MAXW; j++) s[j] = 0.0;
-    for (int b = b0; b < b1; b++) {
+    int b = tid;
+    for (; b + 3 * 256 < nb; b += 4 * 256) {
+        double v[4][SUM_MAXW];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int j = 0; j < SUM_MAXW; j++) v[u][j] = j < width ? part[(long)(b + u * 256) * width + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int j = 0; j < SUM_MAXW; j++) s[j] += v[u][j];
+    }
+    for (; b < nb; b += 256) {
 #pragma unroll
         for (int j = 0; j < SUM_MAXW; j++)
             if (j < width) s[j] += part[(long)b * width + j];
     }
 #pragma unroll
-    for (int j = 0; j < SUM_MAXW; j++)
-        if (j < width) sh[j][threadIdx.x] = s[j];
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int j = 0; j < width; j++) sh[j][threadIdx.x] += sh[j][threadIdx.x + o];
-        __syncthreads();
+    for (int j = 0; j < SUM_MAXW; j++) {
+        double v = s[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) sh[wave][j] = v;
     }
-    if ((int)threadIdx.x < width) out[threadIdx.x] = sh[threadIdx.x][0];
+    __syncthreads();
+    if (tid < width) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += sh[w][tid];
+        out[tid] = t;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_sum_rows(const double *__restrict__ part, int nb, int width,
@@ -766,3 +782,4 @@ cbct_status cbct_launch_axpy_batch(const AxpyReq *r, int n, hipStream_t s) {
     }
     return CBCT_OK;
 }
+

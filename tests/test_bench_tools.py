@@ -93,3 +93,23 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_sq_summary(tmp_path, capsys):
+    """VALU-at-peak = SQ_INSTS_VALU / (256 CUs x 2.4 GHz); its share of the kernel's duration."""
+    rows = []
+    n_valu = 256 * 2.4e9 * 500e-6  # 500 us of VALU issue at peak
+    for d, (cn, v) in enumerate([("SQ_INSTS_VALU", n_valu), ("SQ_INSTS_LDS", 1000.0), ("SQ_LDS_BANK_CONFLICT", 500.0),
+                                 ("SQ_ACTIVE_INST_VALU", 1.0), ("SQ_ACTIVE_INST_LDS", 1.0), ("SQ_BUSY_CYCLES", 1.0),
+                                 ("SQ_WAVE_CYCLES", 1.0), ("SQ_WAVES", 1.0)]):
+        rows += [(1, "void (anonymous namespace)::k_adj_gather_staged<32, 320>(float const*)", cn, v / 2)] * 2
+    _db(str(tmp_path / "s"), rows, kernels=[
+        ("void (anonymous namespace)::k_adj_gather_staged<32, 320>(float const*)", 1_000_000, 72, 52120, 1, 1, 1)])
+    bench.sq_summary(str(tmp_path / "s"))
+    line = [ln for ln in capsys.readouterr().out.splitlines() if ln.strip().startswith("k_adj_gather_staged")][0]
+    f = line.split()
+    assert float(f[1]) == pytest.approx(n_valu, rel=1e-3)
+    assert float(f[4]) == pytest.approx(0.5)            # bank-conflict cycles per LDS instruction
+    assert float(f[5]) == pytest.approx(1000.0)         # duration, us
+    assert float(f[6]) == pytest.approx(500.0, rel=1e-3)  # VALU at peak, us
+    assert f[7] == "50%"
