@@ -257,6 +257,17 @@ cbct_status cbct_tv_energy_grad_workspace_size(const cbct_plan *plan, size_t *by
 cbct_status cbct_tv_energy_grad(cbct_plan *plan, int level, double tv_eps, const float *d_f, float *d_grad,
                                 double *h_sum, void *d_ws, size_t ws_bytes, cbct_stream_t stream);
 
+/* cbct_tv_energy_grad without a workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that forbid allocation): the same kernels and the same
+ * result, with the partial sums in a 256 KB scratch array that the library holds per device
+ * until the process ends (set up by cbct_context_create for its device).  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  The call allocates nothing.  INVALID_ARG for
+ * bad arguments, for a plan whose device had no context made, or for a volume whose partial sums
+ * would exceed the scratch. */
+cbct_status cbct_tv_energy_grad_noalloc(cbct_plan *plan, int level, double tv_eps, const float *d_f, float *d_grad,
+                                        double *h_sum, cbct_stream_t stream);
+
 /* Multigrid transfers (Section II.C.3): cell-centred trilinear prolongation of level
  * coarse_level into level coarse_level-1 (3/4 parent + 1/4 neighbour per axis, clamped), and
  * restriction = (1/8) Prol^T from fine_level into fine_level+1.  Detector restriction for

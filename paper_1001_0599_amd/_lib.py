@@ -78,6 +78,7 @@ _SIG = [
     ("cbct_tv_energy_grad_workspace_size", C.c_int, [_VP, C.POINTER(C.c_size_t)]),
     ("cbct_tv_energy_grad", C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, C.POINTER(C.c_double), _VP, C.c_size_t,
                                       _VP]),
+    ("cbct_tv_energy_grad_noalloc", C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, C.POINTER(C.c_double), _VP]),
     ("cbct_prolong", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_restrict", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),
     ("cbct_bin_detector", C.c_int, [_VP, C.c_int, _VP, _VP, _VP]),

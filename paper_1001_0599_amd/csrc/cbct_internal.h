@@ -215,6 +215,12 @@ cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const fl
                                   RofRecord *rec, int rec_cap, int level, int outer, bool init, hipStream_t s);
 
 int cbct_reduce_blocks(const Level &L);
+// Device scratch of cbct_tv_energy_grad_noalloc: a file-scope device array of this size per
+// device, its address looked up once per device (with the device current) by context creation.
+constexpr size_t CBCT_NOALLOC_SCRATCH_BYTES = 256 * 1024;
+constexpr int CBCT_MAX_DEVICES = 64;
+cbct_status cbct_noalloc_scratch_init(int device);
+void *cbct_noalloc_scratch(int device);  // NULL before cbct_noalloc_scratch_init on that device
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s);
 cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, double *partials, double *sum,

@@ -215,6 +215,12 @@ extern "C" cbct_status cbct_context_create(int hip_device, cbct_context **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "context_create: device %d is %s, the library is built for gfx950",
                               hip_device, prop.gcnArchName);
+    {
+        // per device, once: the address of the no-allocation entry point's scratch array
+        DeviceGuard dg(hip_device);
+        cbct_status st = cbct_noalloc_scratch_init(hip_device);
+        if (st) return st;
+    }
     cbct_context *c = new (std::nothrow) cbct_context();
     if (!c) return cbct_set_error(CBCT_ERR_OUT_OF_MEMORY, "context_create: host allocation");
     c->device = hip_device;

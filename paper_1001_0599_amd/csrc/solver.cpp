@@ -572,6 +572,36 @@ extern "C" cbct_status cbct_tv_energy_grad(cbct_plan *p, int level, double tv_ep
     return CBCT_OK;
 }
 
+extern "C" cbct_status cbct_tv_energy_grad_noalloc(cbct_plan *p, int level, double tv_eps, const float *d_f,
+                                                   float *d_grad, double *h_sum, cbct_stream_t stream) {
+    if (!p || !d_f || level < 0 || level >= p->levels || !(tv_eps > 0.0))
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad_noalloc: bad arguments");
+    const Level &L = p->lv[level];
+    // the same partial-sum layout as cbct_tv_energy_grad, in the device's scratch array
+    const size_t need = sizeof(double) * ((size_t)CBCT_RED_BLOCKS * 3 + 8);
+    if (need > CBCT_NOALLOC_SCRATCH_BYTES || (size_t)cbct_reduce_blocks(L) > (size_t)CBCT_RED_BLOCKS)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad_noalloc: needs %zu bytes of scratch, the maximum is %zu",
+                              need, CBCT_NOALLOC_SCRATCH_BYTES);
+    double *part = (double *)cbct_noalloc_scratch(p->device);
+    if (!part)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "tv_energy_grad_noalloc: no context was created for device %d",
+                              p->device);
+    double *sums = part + CBCT_RED_BLOCKS * 3;
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(p->device);
+    // every partial the final sum reads is written by this call's gradient (or energy) pass:
+    // nothing in the scratch needs clearing first
+    cbct_status st;
+    if (d_grad) st = cbct_launch_tv_grad(L, tv_eps, d_f, nullptr, d_grad, 0.0, 1.0, part, sums, s);
+    else st = cbct_launch_tv_energy(L, tv_eps, d_f, part, sums, s);
+    if (st) return st;
+    if (h_sum) {
+        CBCT_HIP(hipMemcpyAsync(h_sum, sums, sizeof(double), hipMemcpyDeviceToHost, s));
+        CBCT_HIP(hipStreamSynchronize(s));
+    }
+    return CBCT_OK;
+}
+
 extern "C" cbct_status cbct_prolong(const cbct_plan *p, int coarse_level, const float *d_c, float *d_f,
                                     cbct_stream_t stream) {
     if (!p || !d_c || !d_f || coarse_level < 1 || coarse_level >= p->levels)

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "cbct_internal.h"
 
@@ -783,3 +784,32 @@ cbct_status cbct_launch_axpy_batch(const AxpyReq *r, int n, hipStream_t s) {
     return CBCT_OK;
 }
 
+// ---- scratch of the no-allocation TV energy / gradient entry point --------------------------
+// The fixed-order partial sums of the gradient pass (3 doubles per work-group of the reduction
+// grid) and the final sums live in this file-scope device array instead of a caller workspace.
+// Each device holds its own copy until the process ends; host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[CBCT_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[CBCT_MAX_DEVICES];
+
+cbct_status cbct_noalloc_scratch_init(int device) {
+    if (device < 0 || device >= CBCT_MAX_DEVICES)
+        return cbct_set_error(CBCT_ERR_INVALID_ARG, "scratch: device %d beyond %d", device, CBCT_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return CBCT_OK;
+    int cur = -1;
+    CBCT_HIP(hipGetDevice(&cur));
+    if (cur != device) return cbct_set_error(CBCT_ERR_INTERNAL, "scratch: device %d is not current", device);
+    void *p = nullptr;
+    CBCT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = p;
+    return CBCT_OK;
+}
+
+void *cbct_noalloc_scratch(int device) {
+    if (device < 0 || device >= CBCT_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
