@@ -207,10 +207,50 @@ def serving_run(n_requests):
     return res
 
 
+def small_solves():
+    """Solves that are bound by launches and the ROF loop's decisions rather than by bandwidth:
+    the 32^3 / 16-view cube (20 iterations), the low-dose 32^3 sweep (3 levels x 100 iterations,
+    lambda 0.02 / 0.05 / 0.1, I0 = 2e3) and a 128^3 / 60-view volume (20 iterations, its ROF loop
+    on gated launch chains); milliseconds per solve, medians of repeated solves."""
+    import numpy as np
+    import torch
+
+    import cbct_synth as S
+    from paper_1001_0599_amd.ops import Plan
+
+    def timed(plan, y, lam, iters, reps):
+        out = torch.empty(plan.vol_shape(0), device="cuda")
+        plan.reconstruct(y, lam=lam, iters=iters, out=out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            plan.reconstruct(y, lam=lam, iters=iters, out=out)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    def noisy(g, seeds, i0):
+        ph = S.make_phantom(g, seeds[0])
+        return S.poisson_log_torch(S.analytic_projections_torch(g, ph, "cuda"), i0, seeds[1]).float().contiguous()
+
+    res = {}
+    c = S.CONFIGS["cube32"]
+    res["cube32_16views_20it_ms"] = timed(Plan(c["geometry"], levels=1), noisy(c["geometry"], c["seeds"], c["I0"]),
+                                         c["lam"], c["iters"], 20)
+    c = S.CONFIGS["lowdose32"]
+    plan = Plan(c["geometry"], levels=c["levels"])
+    y = noisy(c["geometry"], c["seeds"], c["I0"])
+    res["lowdose32_3x100it_ms"] = {str(lam): timed(plan, y, lam, c["iters"], 3) for lam in c["lam"]}
+    g = S.CONFIGS["batch8x128"]["geometry"]
+    res["vol128_60views_20it_ms"] = timed(Plan(g, levels=1), noisy(g, (41, 49), 1e5), 0.05, [20], 5)
+    return res
+
+
 def kernels_only():
     """One launch each of a plain 256 MB copy and the hot kernels at the 512x512x64 / 40-view size:
     P (k_forward_runs), P^T (k_adj_profiles, k_adj_gather_staged, k_adj_combine), the Eq. 6 backprojector, the
-    Siddon pair, and one Step 2 solve (k_tv_grad, k_tv_trial, ...); the driver for hardware-counter
+    Siddon pair, and the TV passes (k_tv_grad, k_tv_trial<1>); the driver for hardware-counter
     runs, whose records `--counter-summary` turns into the traffic and L2 hit-rate table."""
     import torch
 
@@ -240,10 +280,10 @@ def kernels_only():
     plan.forward_siddon(fv, out=proj, workspace=sws)
     plan.adjoint_siddon(y, out=vol, workspace=sws)
     del sws
-    plan.tv_prox(fv, 0.05, 1e-3)
-    # one outer iteration of the solver: the residual projector fused with the adjoint's profile
-    # pass, and the gather alone in Step 1
-    plan.reconstruct(y, lam=0.05, iters=[1])
+    # the TV passes: one gradient pass, and one ROF iteration of the host-driven loop (a replayed
+    # decision selects it): gradient, the first trial window, decision, update
+    plan.tv_energy_grad(fv)
+    plan.tv_prox(fv, 0.05, 1e-3, replay=[(0, 1)])
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": 2 * 4 * a.numel()}))
 
@@ -614,6 +654,8 @@ def main():
         "recon_s_siddon_pair": recon_sid_s, "recon_s_siddon_p_eq6_step1": recon_sid6_s,
         "roofline": roofline,
     }
+    log("launch-bound solves: 32^3, low-dose 32^3 sweep, 128^3")
+    res["solves"] = small_solves()
     if args.serving:
         res["serving"] = serving_run(args.serving)
     if not args.no_cpu_baseline:

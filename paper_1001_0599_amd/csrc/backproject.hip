@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256)
     __shared__ float4 zs[(GS_ROWS + 1) * GS_PITCH];  // + one spill row for the staging's idle slots
     __shared__ GsCol ci[GS_CC];
     __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
-    __shared__ int rowsrc[GS_ROWS];  // profile offset of each staged row, in float4 units
+    __shared__ long rowsrc[GS_ROWS];  // profile offset of each staged row
 
     int tx, ty, tzg;
     tile_of(tx, ty, tzg);
@@ -285,40 +285,38 @@ __global__ void __launch_bounds__(256)
             for (int R0 = 0; R0 < total; R0 += GS_ROWS) {
                 const int nrows = min(GS_ROWS, total - R0);
                 // profile offsets of this batch's rows
-                if (tid < nc) {
-                    const int r_a = max(cnt[tid], R0), r_b = min(cnt[tid + 1], R0 + nrows);
-                    const long z0 = ci[tid].zrow - (long)cnt[tid] * A.nz;
-                    for (int r = r_a; r < r_b; r++) rowsrc[r - R0] = (int)((z0 + (long)r * A.nz) >> 2);
+                // four threads per column (a chunk holds at most 64)
+                if (tid < 4 * nc) {
+                    const int t = tid >> 2;
+                    const int r_a = max(cnt[t], R0), r_b = min(cnt[t + 1], R0 + nrows);
+                    const long z0 = ci[t].zrow - (long)cnt[t] * A.nz;
+                    for (int r = r_a + (tid & 3); r < r_b; r += 4) rowsrc[r - R0] = z0 + (long)r * A.nz;
                 }
                 __syncthreads();
                 // stage the rows: 8 lanes per 128-byte row; every load of the batch is issued
                 // before the first LDS store, so the batch pays one memory latency
                 {
-                    // slot j of this thread holds float4 `sl` of batch row row0 + RSTEP j (the
-                    // addresses are per-thread constants plus immediates)
                     constexpr int PER = (GS_ROWS * GS_Q + 255) / 256;
-                    constexpr int RSTEP = 256 >> GS_QS;
-                    static_assert(PER <= 10, "one asm statement consumes the batch's loads");
-                    const int row0 = tid >> GS_QS, sl = tid & (GS_Q - 1);
-                    const float4 *Z4 = reinterpret_cast<const float4 *>(Z);
-                    float4 v[10];
+                    const int items = nrows * GS_Q;  // > 0
+                    float4 v[PER];
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
-                        // slots past the batch load its last row again (no branch between the loads)
-                        const int rr = min(row0 + RSTEP * j, nrows - 1);
-                        v[j] = Z4[(unsigned)rowsrc[rr] + (unsigned)sl];
+                        // items past the batch load its last row again (no branch between the loads)
+                        const int it = min(tid + 256 * j, items - 1);
+                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1)));
                     }
+                    // all loads in flight before the first store: an empty asm statement consumes
+                    // every loaded word here, so the compiler cannot sink (or split) each load
+                    // down to its store; idle slots store into the spill row
+                    float dep = 0.0f;
 #pragma unroll
-                    for (int j = PER; j < 10; j++) v[j] = v[0];
-                    // every load of the batch is in flight before the first store: one empty asm
-                    // statement consumes a word of each (a load is one whole float4), so none can be
-                    // sunk down to its store; idle slots store into the spill row
-                    asm volatile("" ::"v"(v[0].x), "v"(v[1].x), "v"(v[2].x), "v"(v[3].x), "v"(v[4].x), "v"(v[5].x),
-                                 "v"(v[6].x), "v"(v[7].x), "v"(v[8].x), "v"(v[9].x));
+                    for (int j = 0; j < PER; j++) dep += (v[j].x + v[j].y) + (v[j].z + v[j].w);
+                    asm volatile("" ::"v"(dep));
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
-                        const int r = row0 + RSTEP * j;
-                        zs[(r < nrows ? r : GS_ROWS) * GS_PITCH + sl] = v[j];
+                        const int it = tid + 256 * j;
+                        const int r = it < items ? (it >> GS_QS) : GS_ROWS;
+                        zs[r * GS_PITCH + (it & (GS_Q - 1))] = v[j];
                     }
                 }
                 __syncthreads();

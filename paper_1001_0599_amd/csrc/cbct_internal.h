@@ -195,10 +195,12 @@ struct RofControl {
     int pad;         // in the host-mapped copy: the decision call's sequence number, written last
 };
 
-// Step 2 of a small volume in one work-group (no host round trip per ROF iteration): state and
-// per-iteration records kept in device memory across the outer iterations of a level.
-constexpr long CBCT_SMALL_ROF_VOX = 65536;  // volumes up to this many voxels take that path
-struct RofSmallState {
+// Step 2 on the device keeps its records, the replay position and a non-finite flag in device
+// memory across the outer iterations of a level (read back once per level).  Volumes of at most
+// CBCT_SMALL_ROF_VOX voxels run the whole loop in one work-group (for 16^3 and smaller it beats
+// launching the passes: 8^3 / 16^3 levels of a low-dose cascade); larger ones run gated chains.
+constexpr long CBCT_SMALL_ROF_VOX = 4096;
+struct RofLog {
     int n_rec;       // records appended so far (also those beyond the buffer)
     int replay_pos;  // replay records consumed
     int status;      // 1: a non-finite energy stopped the loop
@@ -209,9 +211,52 @@ struct RofRecord {
     int level, outer, inner, m;  // m = -1: no admissible step
 };
 static_assert(sizeof(RofRecord) == 40, "RofRecord layout");
+
+// Step 2 of a larger volume as flag-gated launch chains: the host enqueues steps (apply the last
+// accepted step, a new gradient, one trial window, the decision) ahead of the decisions; every
+// pass reads this state first and does nothing once the loop has ended or when the step does not
+// need it.  The decision kernel updates it; records and the replay position are those of
+// RofLog.
+struct RofGate {
+    int run;      // 1 while the loop continues
+    int m0;       // first backtracking exponent of the next trial window
+    int apply;    // the next step starts with u -= s d (s of the accepted decision in RofControl)
+    int grad;     // the next step computes a new gradient
+    int it;       // ROF iteration of the next decision
+    int pending;  // the loop ended on an accepted step that is not applied to u
+    int pad[2];
+};
+// host-mapped word a gated decision writes last: (sequence << 2) | (non-finite << 1) | running
+__host__ __device__ inline int cbct_gate_word(int seq, int status, int run) { return (seq << 2) | (status << 1) | run; }
+constexpr int CBCT_GATE_SEQ_MASK = 0x1fffffff;  // sequence numbers wrap within 29 bits
+struct RofStepArgs {
+    double eps, lambda, t, c_armijo, alpha, tol;
+    int max_iter, max_bt;
+    float *u;
+    const float *g;
+    float *d;
+    double *part;  // gradient partials at part, trial partials at part + 3 CBCT_RED_BLOCKS
+    double *sums;  // [0..2] gradient sums, [3..] trial sums
+    RofControl *ctl;
+    RofGate *gate;
+    RofLog *st;
+    const int *replay;
+    int replay_len;
+    RofRecord *rec;  // NULL: no records (the count still advances)
+    int rec_cap, level, outer;
+    int *mirror;  // host-mapped word (device address), or NULL
+    int seq;
+};
+// resets the gate for a new loop; with init_state also the records and replay position
+cbct_status cbct_launch_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, bool init_state,
+                                      hipStream_t s);
+cbct_status cbct_launch_rof_step_gated(const Level &L, const RofStepArgs &a, hipStream_t s);
+// u -= s d when the gated loop ended on a pending accepted step
+cbct_status cbct_launch_axpy_pending(float *u, const float *d, const RofControl *ctl, const RofGate *gate, long n,
+                                     hipStream_t s);
 cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const float *g, float *d, double lambda,
                                   double t, double c_armijo, double alpha, double tol, int max_iter, int max_bt,
-                                  const int *replay, int replay_len, int replay_pos, RofSmallState *st,
+                                  const int *replay, int replay_len, int replay_pos, RofLog *st,
                                   RofRecord *rec, int rec_cap, int level, int outer, bool init, hipStream_t s);
 
 int cbct_reduce_blocks(const Level &L);
@@ -240,7 +285,8 @@ struct SolveBufs {
     float *ypyr[8];
     double *part, *sums, *eng;
     RofControl *ctl;
-    RofSmallState *sst;  // Step 2 on the device for small levels: state and records
+    RofLog *sst;  // Step 2 on the device: records and replay position
+    RofGate *gate;       // Step 2 as gated launch chains (larger levels)
     RofRecord *rec;
     int rec_cap;
     int *replay;         // device copy of params.replay (2 ints per record)
@@ -254,34 +300,11 @@ cbct_status cbct_solve_schur(cbct_plan *p, int level, int projector, const Solve
 // requests; each request's work-groups run the solo kernel's body on that request's buffers and
 // grid, so its results are bitwise those of a solo launch.
 constexpr int CBCT_MAXB = 16;  // requests per batched launch
-struct TvReq {                 // one request of a batched TV / ROF launch
-    const Level *L;
-    double eps, lambda, t, alpha;
-    const float *u, *g;
-    float *d;
-    double *partials, *sums;
-    int m0;  // trial passes: first backtracking exponent of the window
-};
-// d, E_R and G sums (grad + fixed-order sum), trial sums of M (1 or CBCT_TRIALS) step sizes
-cbct_status cbct_launch_tv_grad_batch(const TvReq *r, int n, hipStream_t s);
-cbct_status cbct_launch_tv_trial_batch(const TvReq *r, int n, int M, hipStream_t s);
-struct DecideReq {
-    const double *sums;
-    int m0, M;
-    long nvox;
-    double lambda, t, c_armijo, alpha;
-    int max_bt;
-    RofControl *ctl, *mirror;
-    int seq;
-};
-cbct_status cbct_launch_rof_decide_batch(const DecideReq *r, int n, hipStream_t s);
-struct AxpyReq {
-    float *u;
-    const float *d;
-    const RofControl *ctl;
-    long n;
-};
-cbct_status cbct_launch_axpy_batch(const AxpyReq *r, int n, hipStream_t s);
+// one gated Step 2 step of several requests (each with its own level, buffers and loop state)
+cbct_status cbct_launch_rof_step_gated_batch(const Level *const *L, const RofStepArgs *a, int n, hipStream_t s);
+// resets several requests' gates (with init_state also their records and replay positions)
+cbct_status cbct_launch_rof_gate_init_batch(RofGate *const *gate, RofLog *const *st, int n, bool init_state,
+                                            hipStream_t s);
 struct ClampReq {
     const Level *L;
     const float *u, *d;

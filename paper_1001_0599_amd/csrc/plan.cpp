@@ -168,9 +168,6 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
         zoff = L.adj_part_off + (long)L.adj_vsplit * L.nvox();
     }
     L.z_floats = std::max(zoff, 4L);
-    if (cbct_adj_staged_tz(L.nz) && L.z_floats / 4 > 0x7fffffffL)
-        return cbct_set_error(CBCT_ERR_INVALID_ARG, "level %d: adjoint profiles of %.1f GB exceed the gather's 32 GB "
-                              "addressing", l, 4e-9 * (double)L.z_floats);
     AdjArgs &A = L.adj;
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
     A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;

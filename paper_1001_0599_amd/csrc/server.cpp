@@ -11,10 +11,14 @@
 // through the same phase sequence of Algorithm A1, one outer iteration per round:
 //   residual P of all requests            one batched launch (per projector configuration)
 //   Step 1, g = f - kappa P^T r            per request (its own grid and profile workspace)
-//   Step 2, the ROF loop                   per ROF iteration: one batched gradient pass, one
-//                                          batched trial pass per search window, one batched
-//                                          decision kernel, ONE host read of all the requests'
-//                                          decisions, one batched update
+//   Step 2, the ROF loop                   gated steps of all requests (apply the accepted step,
+//                                          gradient, one trial window, decision: four batched
+//                                          launches) enqueued two ahead of the decisions; each
+//                                          request's passes read its loop state and idle once its
+//                                          loop has ended; the host reads one word per request
+//                                          and step and drops finished requests from later steps
+//                                          (requests of at most 2^16 voxels run their whole loop
+//                                          in one work-group instead)
 //   Step 3, f = max(u, 0)                  one batched launch
 // There are three engines, for volumes up to 2^18.5 voxels, up to 2^21.5 and larger, on their own
 // streams: a round costs about as much as its largest request, so requests of similar size share
@@ -105,10 +109,12 @@ struct Request {
     int level = 0, k = 0, slot = -1;
     double t = 0.0;
     float kappa = 0.0f;
-    bool small = false, small_init = false;
-    // ROF state of the current outer iteration
-    bool rof_active = false, need_grad = false, pending = false;
-    int rof_it = 0, m0 = 0, seq = 0;
+    bool small = false;
+    bool dev_init = false;  // its device-side Step 2 state (records, replay position, status) is set
+    // Step 2 of the current outer iteration: a gated loop ran (Step 3 applies its pending step);
+    // the sequence numbers of the steps enqueued for it
+    bool pending = false;
+    std::vector<int> seqs;
 };
 
 std::string geom_key(const cbct_geometry_desc &g, const std::vector<double> &angles, int levels) {
@@ -148,13 +154,14 @@ size_t estimate_ws(const cbct_geometry_desc &g, int levels, const std::vector<in
         const size_t lines = (size_t)g.n_views * nu;
         const size_t zs = align256(lines * (size_t)(nx + ny + 3) * nz * 4) / 4 + lines * 4;
         zmax = std::max(zmax, projector == 1 ? zs : zf);
-        if ((long)nx * ny * nz <= CBCT_SMALL_ROF_VOX) rec = std::max(rec, (long)std::max(iters[l], 1) * rof_max_iter);
+        rec = std::max(rec, (long)std::max(iters[l], 1) * rof_max_iter);
     }
     b += align256(4 * zmax);
     int slots = 0;
     for (int l = 0; l < levels; l++) slots += iters[l] + 1;
     b += align256(16 * (size_t)std::max(slots, 1)) + align256(sizeof(RofControl));
-    b += align256(sizeof(RofSmallState)) + align256(sizeof(RofRecord) * (size_t)std::max<long>(rec, 1)) + 256;
+    b += align256(sizeof(RofLog)) + align256(sizeof(RofGate)) +
+         align256(sizeof(RofRecord) * (size_t)std::max<long>(std::min(rec, 1L << 24), 1)) + 256;
     return b;
 }
 
@@ -193,7 +200,7 @@ struct cbct_server {
     std::map<std::string, PlanEntry> plans;
     std::vector<bool> slot_used;
     RofControl *mirror_host = nullptr, *mirror_dev = nullptr;  // host-mapped decision records
-    int seq = 0;
+    std::atomic<int> seq{0};  // sequence numbers of the gated decisions' words
     // counters of the batched phases (for tests and reports)
     std::atomic<uint64_t> batched_launches{0}, batched_items{0};
 };
@@ -410,7 +417,6 @@ cbct_status start_level(Request *r, hipStream_t s, bool first) {
     r->t = t;
     r->kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
     r->small = L.nvox() <= CBCT_SMALL_ROF_VOX && r->b.rec_cap > 0;
-    r->small_init = false;
     r->k = 0;
     return cbct_launch_to_columns(L, r->b.f, r->b.ft, s);
 }
@@ -452,7 +458,10 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
         const Level &L = r->pe->plan->lv[r->level];
         if ((st = cbct_launch_adjoint(L, r->b.r, r->b.f, r->kappa, r->b.g, r->b.z, st_, true, r->b.u))) return st;
     }
-    // Step 2
+    // Step 2: the small requests ran their loop in one work-group above; the others run gated
+    // steps in shared launches (see cbct_launch_rof_step_gated_batch), AHEAD steps in front of
+    // the decisions, and leave the batch when a decision ends their loop
+    constexpr int AHEAD = 2;
     std::vector<Request *> rof;
     for (Request *r : act) {
         r->pending = false;
@@ -461,104 +470,124 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
             const cbct_solve_params &p = r->p;
             if ((st = cbct_launch_rof_small(L, p.tv_eps, r->b.u, r->b.g, r->b.d, p.lambda, r->t, p.armijo_c,
                                             p.backtrack, p.rof_tol, p.rof_max_iter, p.rof_max_backtrack, nullptr, 0, 0,
-                                            r->b.sst, nullptr, r->b.rec_cap, r->level, r->k, !r->small_init, st_)))
+                                            r->b.sst, nullptr, r->b.rec_cap, r->level, r->k, !r->dev_init, st_)))
                 return st;
-            r->small_init = true;
+            r->dev_init = true;
             continue;
         }
-        r->rof_active = r->p.rof_max_iter > 0;
-        r->need_grad = true;
-        r->rof_it = 0;
-        r->m0 = 0;
-        if (r->rof_active) rof.push_back(r);
+        if (r->p.rof_max_iter > 0) rof.push_back(r);
     }
-    while (!rof.empty()) {
-        std::vector<TvReq> grad, t1, t4;
-        std::vector<DecideReq> dec;
+    if (!rof.empty()) {
+        // new loops; the records and replay position (unused here) are reset once per request
+        std::vector<RofGate *> gates;
+        std::vector<RofLog *> sts;
+        std::vector<Request *> fresh_state, kept_state;
+        for (Request *r : rof) (r->dev_init ? kept_state : fresh_state).push_back(r);
+        for (int pass = 0; pass < 2; pass++) {
+            const auto &grp = pass == 0 ? fresh_state : kept_state;
+            if (grp.empty()) continue;
+            gates.clear();
+            sts.clear();
+            for (Request *r : grp) {
+                gates.push_back(r->b.gate);
+                sts.push_back(r->b.sst);
+                r->dev_init = true;
+            }
+            if ((st = cbct_launch_rof_gate_init_batch(gates.data(), sts.data(), (int)grp.size(), pass == 0, st_)))
+                return st;
+        }
+        long max_steps = 0;
         for (Request *r : rof) {
-            const Level &L = r->pe->plan->lv[r->level];
-            const TvReq tr{&L, r->p.tv_eps, r->p.lambda, r->t, r->p.backtrack, r->b.u, r->b.g, r->b.d, r->b.part,
-                           r->b.sums, r->m0};
-            if (r->need_grad) grad.push_back(tr);
-            // the first window tries the full step only (accepted almost always), later windows
-            // CBCT_TRIALS step sizes per pass: as the solo loop
-            (r->m0 == 0 ? t1 : t4).push_back(tr);
-            r->seq = ++s->seq;
-            if (s->seq == 0x7fffffff) s->seq = 0;
-            dec.push_back(DecideReq{r->b.sums, r->m0, r->m0 == 0 ? 1 : CBCT_TRIALS, L.nvox(), r->p.lambda, r->t,
-                                    r->p.armijo_c, r->p.backtrack, r->p.rof_max_backtrack, r->b.ctl,
-                                    s->mirror_dev ? s->mirror_dev + r->slot : nullptr, r->seq});
+            r->pending = true;  // the clamp applies the last decision's step if it accepted one
+            r->seqs.clear();
+            max_steps = std::max(max_steps, (long)r->p.rof_max_iter * (2 + r->p.rof_max_backtrack / CBCT_TRIALS));
         }
-        // the trial pass of a request needs its gradient pass: every gradient before any trial
-        if (!grad.empty()) {
-            if ((st = cbct_launch_tv_grad_batch(grad.data(), (int)grad.size(), st_))) return st;
-            s->batched_launches++;
-            s->batched_items += grad.size();
-        }
-        if (!t1.empty() && (st = cbct_launch_tv_trial_batch(t1.data(), (int)t1.size(), 1, st_))) return st;
-        if (!t4.empty() && (st = cbct_launch_tv_trial_batch(t4.data(), (int)t4.size(), CBCT_TRIALS, st_))) return st;
-        if ((st = cbct_launch_rof_decide_batch(dec.data(), (int)dec.size(), st_))) return st;
-        s->batched_launches += 2;
-        s->batched_items += 2 * rof.size();
-        // one read of every request's decision
-        std::vector<RofControl> c(rof.size());
-        if (s->mirror_host) {
-            for (size_t q = 0; q < rof.size(); q++) {
-                const volatile int *p = &s->mirror_host[rof[q]->slot].pad;
-                const auto t0 = clk::now();
-                bool seen = false;
-                for (int spin = 0;; spin++) {
-                    if (*p == rof[q]->seq) {
-                        seen = true;
-                        break;
-                    }
-                    if ((spin & 1023) == 1023 && clk::now() - t0 > std::chrono::milliseconds(20)) break;
+        std::vector<Request *> active = rof;
+        std::vector<const Level *> lv;
+        std::vector<RofStepArgs> args;
+        long issued = 0, known = 0;
+        while (!active.empty()) {
+            while (issued < max_steps && issued < known + AHEAD) {
+                lv.clear();
+                args.clear();
+                for (Request *r : active) {
+                    const Level &L = r->pe->plan->lv[r->level];
+                    RofStepArgs a{};
+                    a.eps = r->p.tv_eps;
+                    a.lambda = r->p.lambda;
+                    a.t = r->t;
+                    a.c_armijo = r->p.armijo_c;
+                    a.alpha = r->p.backtrack;
+                    a.tol = r->p.rof_tol;
+                    a.max_iter = r->p.rof_max_iter;
+                    a.max_bt = r->p.rof_max_backtrack;
+                    a.u = r->b.u;
+                    a.g = r->b.g;
+                    a.d = r->b.d;
+                    a.part = r->b.part;
+                    a.sums = r->b.sums;
+                    a.ctl = r->b.ctl;
+                    a.gate = r->b.gate;
+                    a.st = r->b.sst;
+                    a.rec_cap = r->b.rec_cap;
+                    a.level = r->level;
+                    a.outer = r->k;
+                    a.mirror = s->mirror_dev ? &s->mirror_dev[r->slot].pad : nullptr;
+                    a.seq = (s->seq.fetch_add(1) + 1) & CBCT_GATE_SEQ_MASK;
+                    r->seqs.push_back(a.seq);
+                    lv.push_back(&L);
+                    args.push_back(a);
                 }
-                if (!seen) CBCT_HIP(hipStreamSynchronize(st_));
-                std::atomic_thread_fence(std::memory_order_acquire);
-                std::memcpy(&c[q], &s->mirror_host[rof[q]->slot], sizeof(RofControl));
+                if ((st = cbct_launch_rof_step_gated_batch(lv.data(), args.data(), (int)args.size(), st_))) return st;
+                s->batched_launches += 4;
+                s->batched_items += 4 * args.size();
+                issued++;
             }
-        } else {
-            for (size_t q = 0; q < rof.size(); q++)
-                CBCT_HIP(hipMemcpyAsync(&c[q], rof[q]->b.ctl, sizeof(RofControl), hipMemcpyDeviceToHost, st_));
-            CBCT_HIP(hipStreamSynchronize(st_));
-        }
-        std::vector<AxpyReq> ax;
-        std::vector<Request *> next;
-        for (size_t q = 0; q < rof.size(); q++) {
-            Request *r = rof[q];
-            const RofControl &cq = c[q];
-            if (cq.accepted == 0 && cq.next_m0 > r->m0) {  // search the next window, same gradient
-                r->m0 = cq.next_m0;
-                r->need_grad = false;
-                next.push_back(r);
-                continue;
+            if (known >= issued) break;  // every step a loop can take has run
+            // the decisions of step `known` (or later ones) of every active request
+            std::vector<int> words(active.size(), 0);
+            if (s->mirror_host) {
+                for (size_t q = 0; q < active.size(); q++) {
+                    Request *r = active[q];
+                    const volatile int *p = &s->mirror_host[r->slot].pad;
+                    const int want = r->seqs[known];  // every active request is in every step so far
+                    const auto t0 = clk::now();
+                    bool seen = false;
+                    for (int spin = 0;; spin++) {
+                        const int w = *p;
+                        if ((((w >> 2) - want) & CBCT_GATE_SEQ_MASK) < (CBCT_GATE_SEQ_MASK >> 1)) {
+                            words[q] = w;
+                            seen = true;
+                            break;
+                        }
+                        if ((spin & 1023) == 1023 && clk::now() - t0 > std::chrono::milliseconds(20)) break;
+                    }
+                    if (!seen) {
+                        CBCT_HIP(hipStreamSynchronize(st_));
+                        words[q] = *p;
+                    }
+                }
+            } else {
+                // no host-mapped words: read the loop states after the enqueued steps
+                CBCT_HIP(hipStreamSynchronize(st_));
+                for (size_t q = 0; q < active.size(); q++) {
+                    RofGate gs;
+                    RofLog ss;
+                    CBCT_HIP(hipMemcpy(&gs, active[q]->b.gate, sizeof(gs), hipMemcpyDeviceToHost));
+                    CBCT_HIP(hipMemcpy(&ss, active[q]->b.sst, sizeof(ss), hipMemcpyDeviceToHost));
+                    words[q] = cbct_gate_word(0, ss.status ? 1 : 0, gs.run);
+                }
             }
-            if (!std::isfinite(cq.e0) || !std::isfinite(cq.G))
-                return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (request %llu)",
-                                      (unsigned long long)r->ticket);
-            r->rof_active = false;
-            if (cq.accepted != 1) continue;  // Eq. 5 held for no step: keep u
-            const bool stop = cq.e0 == 0.0 || cq.G == 0.0 || std::fabs(cq.e_trial - cq.e0) / cq.e0 < r->p.rof_tol ||
-                              r->rof_it + 1 == r->p.rof_max_iter;
-            if (stop) {
-                r->pending = true;  // Step 3 applies the accepted step
-                continue;
+            std::vector<Request *> next;
+            for (size_t q = 0; q < active.size(); q++) {
+                if (words[q] & 2)
+                    return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (request %llu)",
+                                          (unsigned long long)active[q]->ticket);
+                if (words[q] & 1) next.push_back(active[q]);
             }
-            const Level &L = r->pe->plan->lv[r->level];
-            ax.push_back(AxpyReq{r->b.u, r->b.d, r->b.ctl, L.nvox()});
-            r->rof_active = true;
-            r->rof_it++;
-            r->m0 = 0;
-            r->need_grad = true;
-            next.push_back(r);
+            active.swap(next);
+            known++;
         }
-        if (!ax.empty()) {
-            if ((st = cbct_launch_axpy_batch(ax.data(), (int)ax.size(), st_))) return st;
-            s->batched_launches++;
-            s->batched_items += ax.size();
-        }
-        rof.swap(next);
     }
     // Step 3 (with the last ROF update when it is pending)
     std::vector<ClampReq> cl(n);
@@ -638,8 +667,8 @@ void engine_main(cbct_server *s, int cls) {
             if (!finished.empty()) {
                 cbct_status sst = hipStreamSynchronize(stream) == hipSuccess ? CBCT_OK : CBCT_ERR_HIP;
                 for (Request *r : finished) {
-                    if (!sst && r->small) {
-                        RofSmallState ss;
+                    if (!sst && r->dev_init) {
+                        RofLog ss;
                         if (hipMemcpy(&ss, r->b.sst, sizeof(ss), hipMemcpyDeviceToHost) == hipSuccess && ss.status)
                             sst = cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (device-side Step 2)");
                     }

@@ -27,8 +27,10 @@ namespace {
 // staged through a runtime buffer on every ROF iteration).  One slot per host thread (the server
 // runs solves on several threads), allocated on first use and never freed: a free from a
 // thread-exit destructor could run after the HIP runtime has shut down.
+// The same allocation holds the word of the gated loop's decisions, on its own cache line.
 struct MappedSlot {
     RofControl *host = nullptr, *dev = nullptr;
+    int *gword_host = nullptr, *gword_dev = nullptr;
 };
 
 MappedSlot mapped_ctl() {
@@ -37,10 +39,13 @@ MappedSlot mapped_ctl() {
     if (!tried) {
         tried = true;
         void *h = nullptr, *d = nullptr;
-        if (hipHostMalloc(&h, sizeof(RofControl), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+        if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
             hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
             slot.host = (RofControl *)h;
             slot.dev = (RofControl *)d;
+            slot.gword_host = (int *)((char *)h + 128);
+            slot.gword_dev = (int *)((char *)d + 128);
+            *slot.gword_host = 0;
         } else {
             (void)hipGetLastError();  // fall back to copies; do not leave the error pending
         }
@@ -49,11 +54,35 @@ MappedSlot mapped_ctl() {
 }
 
 // sequence numbers of the decision records of this host thread (never 0, the value the kernel
-// writes into the record before its fields)
+// writes into the record before its fields; they wrap within the gate word's 29 bits)
 int next_seq() {
     thread_local int n = 0;
-    n = (n == 0x7fffffff) ? 1 : n + 1;
+    n = (n + 1) & CBCT_GATE_SEQ_MASK;
+    if (n == 0) n = 1;
     return n;
+}
+
+// is sequence number a at or after b (within half the ring)
+bool seq_at_or_after(int a, int b) { return ((a - b) & CBCT_GATE_SEQ_MASK) < (CBCT_GATE_SEQ_MASK >> 1); }
+
+// wait until the gate word carries a decision at or after `seq` and return it; after about 20 ms
+// of polling, synchronise the stream (then every enqueued decision has written it)
+cbct_status wait_gate(const int *word, int seq, hipStream_t s, int *out) {
+    const volatile int *p = word;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0;; spin++) {
+        const int w = *p;
+        if (seq_at_or_after(w >> 2, seq)) {
+            *out = w;
+            return CBCT_OK;
+        }
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+    }
+    CBCT_HIP(hipStreamSynchronize(s));
+    const int w = *p;
+    if (!seq_at_or_after(w >> 2, seq)) return cbct_set_error(CBCT_ERR_INTERNAL, "ROF gate: decision %d not seen", seq);
+    *out = w;
+    return CBCT_OK;
 }
 
 // wait until the host-mapped record carries `seq`: true when seen within the polling window
@@ -98,11 +127,11 @@ size_t partial_count(const cbct_plan *p) {
     return m;
 }
 
-// records of the device-side Step 2: at most rof_max_iter per outer iteration of a small level
-int small_rec_cap(const cbct_plan *p, const cbct_solve_params *pr) {
+// records of the device-side Step 2 (both the one-work-group loop and the gated chains), read
+// back at each level's end: at most rof_max_iter per outer iteration of the level
+int dev_rec_cap(const cbct_plan *, const cbct_solve_params *pr) {
     long cap = 0;
-    for (int l = 0; l < pr->levels; l++)
-        if (p->lv[l].nvox() <= CBCT_SMALL_ROF_VOX) cap = std::max(cap, (long)std::max(pr->iters[l], 1) * pr->rof_max_iter);
+    for (int l = 0; l < pr->levels; l++) cap = std::max(cap, (long)std::max(pr->iters[l], 1) * pr->rof_max_iter);
     return (int)std::min<long>(cap, 1L << 24);
 }
 
@@ -129,7 +158,8 @@ Bufs carve(const cbct_plan *p, int levels, int energy_slots, void *ws, int proje
     b.sums = c.take<double>(64);
     b.eng = c.take<double>(2 * (size_t)std::max(energy_slots, 1));
     b.ctl = c.take<RofControl>(1);
-    b.sst = c.take<RofSmallState>(1);
+    b.sst = c.take<RofLog>(1);
+    b.gate = c.take<RofGate>(1);
     b.rec_cap = rec_cap;
     b.rec = c.take<RofRecord>(std::max(rec_cap, 1));
     b.replay = c.take<int>(2 * (size_t)std::max(replay_len, 1));
@@ -220,7 +250,7 @@ struct TraceSink {
 // Reads back the device-side Step 2 of a small level: its state (replay records consumed, a
 // non-finite energy) and, for the caller's statistics, its per-iteration records in order.
 cbct_status flush_small(const Bufs &b, hipStream_t s, TraceSink &sink, int *replay_pos) {
-    RofSmallState st;
+    RofLog st;
     CBCT_HIP(hipMemcpyAsync(&st, b.sst, sizeof(st), hipMemcpyDeviceToHost, s));
     CBCT_HIP(hipStreamSynchronize(s));
     if (replay_pos) *replay_pos = st.replay_pos;
@@ -317,10 +347,82 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
     return CBCT_OK;
 }
 
+// Step 2 of a larger level as flag-gated launch chains: u = ROF(g) from u already holding g.  The
+// steps go out AHEAD at a time in front of the decisions; the host waits for one decision word
+// per step (not per pass), so the device runs the ROF iterations and backtracking windows back to
+// back, and the host stops enqueueing when a decision ends the loop (a step enqueued past the end
+// does nothing).  `first`: the level's first loop (resets the records and replay position).
+// With `apply_pending` an accepted step that ends the loop is applied to u here; otherwise it is
+// left to the caller's Step 3 (the clamp applies it when the last decision accepted a step).
+cbct_status rof_loop_gated(const Level &L, const cbct_solve_params *pr, double t, const Bufs &b, hipStream_t s,
+                           int level, int outer, bool first, int replay_pos, bool records, bool apply_pending) {
+    constexpr int AHEAD = 2;
+    cbct_status st;
+    if ((st = cbct_launch_rof_gate_init(b.gate, b.sst, replay_pos, first, s))) return st;
+    const MappedSlot ms = mapped_ctl();
+    RofStepArgs a{};
+    a.eps = pr->tv_eps;
+    a.lambda = pr->lambda;
+    a.t = t;
+    a.c_armijo = pr->armijo_c;
+    a.alpha = pr->backtrack;
+    a.tol = pr->rof_tol;
+    a.max_iter = pr->rof_max_iter;
+    a.max_bt = pr->rof_max_backtrack;
+    a.u = b.u;
+    a.g = b.g;
+    a.d = b.d;
+    a.part = b.part;
+    a.sums = b.sums;
+    a.ctl = b.ctl;
+    a.gate = b.gate;
+    a.st = b.sst;
+    a.replay = pr->replay ? b.replay : nullptr;
+    a.replay_len = pr->replay ? pr->replay_len : 0;
+    a.rec = records ? b.rec : nullptr;
+    a.rec_cap = b.rec_cap;
+    a.level = level;
+    a.outer = outer;
+    a.mirror = ms.gword_dev;
+    // steps one loop can take: per ROF iteration the first window and at most
+    // ceil(max_bt / CBCT_TRIALS) more
+    const long max_steps = (long)pr->rof_max_iter * (2 + pr->rof_max_backtrack / CBCT_TRIALS);
+    std::vector<int> seqs;
+    long known = 0;  // steps whose decisions left the loop running
+    for (;;) {
+        while ((long)seqs.size() < max_steps && (long)seqs.size() < known + AHEAD) {
+            a.seq = next_seq();
+            seqs.push_back(a.seq);
+            if ((st = cbct_launch_rof_step_gated(L, a, s))) return st;
+        }
+        if (known >= (long)seqs.size()) break;  // every step a loop can take has run
+        int w;
+        if (ms.gword_host) {
+            if ((st = wait_gate(ms.gword_host, seqs[known], s, &w))) return st;
+        } else {
+            // no host-mapped word: read the state after the enqueued steps
+            RofGate gs;
+            RofLog ss;
+            CBCT_HIP(hipMemcpyAsync(&gs, b.gate, sizeof(gs), hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipMemcpyAsync(&ss, b.sst, sizeof(ss), hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipStreamSynchronize(s));
+            w = cbct_gate_word(seqs.back(), ss.status ? 1 : 0, gs.run);
+        }
+        if (w & 2) return cbct_set_error(CBCT_ERR_NONFINITE, "ROF energy is not finite (level %d, outer %d)", level, outer);
+        if (!(w & 1)) break;  // the loop has ended
+        // the word names the latest decision taken: every step up to it left the loop running
+        long idx = known;
+        while (idx + 1 < (long)seqs.size() && seqs[idx] != (w >> 2)) idx++;
+        known = idx + 1;
+    }
+    if (apply_pending && (st = cbct_launch_axpy_pending(b.u, b.d, b.ctl, b.gate, L.nvox(), s))) return st;
+    return CBCT_OK;
+}
+
 }  // namespace
 
 SolveBufs cbct_solve_carve(const cbct_plan *p, const cbct_solve_params *pr, void *ws) {
-    return carve(p, pr->levels, energy_slots(pr), ws, pr->projector, small_rec_cap(p, pr),
+    return carve(p, pr->levels, energy_slots(pr), ws, pr->projector, dev_rec_cap(p, pr),
                  pr->replay ? pr->replay_len : 0);
 }
 
@@ -347,7 +449,7 @@ extern "C" cbct_status cbct_reconstruct_workspace_size(const cbct_plan *p, const
     cbct_status st = check_params(p, pr, "reconstruct_workspace_size");
     if (st) return st;
     if (!bytes) return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct_workspace_size: NULL out");
-    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr, pr->projector, small_rec_cap(p, pr),
+    *bytes = carve(p, pr->levels, energy_slots(pr), nullptr, pr->projector, dev_rec_cap(p, pr),
                    pr->replay ? pr->replay_len : 0).bytes;
     return CBCT_OK;
 }
@@ -363,7 +465,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
     const int levels = pr->levels;
     const int nslots = energy_slots(pr);
     const int proj = pr->projector;
-    Bufs b = carve(p, levels, nslots, d_ws, proj, small_rec_cap(p, pr), pr->replay ? pr->replay_len : 0);
+    Bufs b = carve(p, levels, nslots, d_ws, proj, dev_rec_cap(p, pr), pr->replay ? pr->replay_len : 0);
     if (ws_bytes < b.bytes)
         return cbct_set_error(CBCT_ERR_INVALID_ARG, "reconstruct: workspace %zu < %zu bytes", ws_bytes, b.bytes);
     if (((uintptr_t)d_ws & 255) != 0)
@@ -419,10 +521,10 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
         if (stats) stats->t_used[l] = t;
         const float kappa = (float)(t * 2.0 * (double)L.nvox() / (double)L.nray());
         if ((st = cbct_launch_to_columns(L, b.f, b.ft, s))) return st;
-        // small levels run Step 2 in one work-group on the device: no host round trip per ROF
-        // iteration (the records and the replay position come back once, at the level's end)
+        // Step 2 runs on the device: small levels in one work-group, larger ones as gated launch
+        // chains; the records and the replay position come back once, at the level's end
         const bool small = L.nvox() <= CBCT_SMALL_ROF_VOX && b.rec_cap > 0;
-        bool small_ran = false;
+        bool dev_ran = false;
         double e_prev = 0.0;
         for (int k = 0; k <= pr->iters[l]; k++) {
             const bool last = (k == pr->iters[l]);
@@ -466,18 +568,21 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
                 st = cbct_launch_rof_small(L, pr->tv_eps, b.u, b.g, b.d, pr->lambda, t, pr->armijo_c, pr->backtrack,
                                            pr->rof_tol, pr->rof_max_iter, pr->rof_max_backtrack,
                                            pr->replay ? b.replay : nullptr, pr->replay ? pr->replay_len : 0,
-                                           replay_pos, b.sst, stats ? b.rec : nullptr, b.rec_cap, l, k, !small_ran, s);
+                                           replay_pos, b.sst, stats ? b.rec : nullptr, b.rec_cap, l, k, !dev_ran, s);
                 if (st) return st;
-                small_ran = true;
-            } else if ((st = rof_loop(L, pr, t, b, s, sink, l, k, &replay_pos, true, &pending))) {
-                return st;
+                dev_ran = true;
+            } else if (pr->rof_max_iter > 0) {
+                if ((st = rof_loop_gated(L, pr, t, b, s, l, k, !dev_ran, replay_pos, stats != nullptr, false)))
+                    return st;
+                dev_ran = true;
+                pending = true;  // the clamp applies the last decision's step if it accepted one
             }
             // Step 3 (with the last ROF update when it is pending)
             if ((st = cbct_launch_clamp_columns(L, b.u, b.f, b.ft, s, pending ? b.d : nullptr,
                                                 pending ? b.ctl : nullptr)))
                 return st;
         }
-        if (small_ran && (st = flush_small(b, s, sink, &replay_pos))) return st;
+        if (dev_ran && (st = flush_small(b, s, sink, &replay_pos))) return st;
     }
     CBCT_HIP(hipMemcpyAsync(d_out, b.f, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
     if (stats) {
@@ -536,6 +641,11 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
                                         pr->rof_tol, pr->rof_max_iter, pr->rof_max_backtrack, nullptr, 0, 0, b.sst,
                                         b.rec, b.rec_cap, level, 0, true, s)))
             return st;
+        if ((st = flush_small(b, s, sink, &pos))) return st;
+    } else if (!pr->replay && pr->rof_max_iter > 0 && (!stats || pr->rof_max_iter <= b.rec_cap)) {
+        // gated launch chains, records read back once
+        CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+        if ((st = rof_loop_gated(L, pr, pr->step, b, s, level, 0, true, 0, stats != nullptr, true))) return st;
         if ((st = flush_small(b, s, sink, &pos))) return st;
     } else if ((st = rof_loop(L, pr, pr->step, b, s, sink, level, 0, &pos))) {
         return st;

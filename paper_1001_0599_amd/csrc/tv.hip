@@ -7,9 +7,10 @@
 //   phi(p) = sqrt(|D u(p)|^2 + eps^2),  q(p) = D u(p) / phi(p),
 //   R(u) = mean phi,  N dR/du_p = sum_d (q_d(p - e_d) [p - e_d in grid] - q_d(p)) / h_d.
 // The ROF energy E_R(u) = lambda R(u) + mean((u-g)^2) / (2t) and its normalised gradient
-// d = lambda N dR/du + (u-g)/t are produced by one stencil pass (13 reads per voxel, served by
-// L1/L2; HBM sees u, g in and d out).  Trial energies E_R(u - s_m d) for M step sizes
-// s_m = t alpha^m come from one more pass, so one pass covers several backtracking steps.
+// d = lambda N dR/du + (u-g)/t are produced by one stencil pass (each voxel's q = D u / phi
+// computed once and handed to the neighbours that need it; HBM sees u, g in and d out).  Trial
+// energies E_R(u - s_m d) for M step sizes s_m = t alpha^m come from one more pass, so one pass
+// covers several backtracking steps.
 //
 // Every reduction is two-level and fixed-order: each work-group of a fixed-size grid writes
 // FP64 partial sums, and a single-work-group kernel sums them in order, so results are
@@ -72,7 +73,7 @@ __device__ __forceinline__ float phi_of(float dx, float dy, float dz, float eps2
     return __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2))));
 }
 
-// Work distribution of the TV kernels: lanes run along x (64 per row segment), work-groups take
+// Work distribution of the energy pass: lanes run along x (64 per row segment), work-groups take
 // (row segment, 4 rows) tiles and stride over the (y, z) rows, so there is one division per row
 // and the grid (hence the partial-sum layout) is fixed by the shape.
 struct RowIter {
@@ -97,55 +98,244 @@ __device__ __forceinline__ RowIter row_iter(const TVShape &k, const Blk2 &B) {
     return it;
 }
 
-// d = lambda * N dR/du + (u - g)/t (g may be NULL: then d = N dR/du and lambda is ignored).
-// partials[block] = {sum phi, sum (u-g)^2, sum d^2}.
-__device__ __forceinline__ void tv_grad_body(const float *__restrict__ u, const float *__restrict__ g,
+// ---- tiled passes: d and the trial energies with the stencil values computed once per voxel ----
+// A wave owns a work item: 64 consecutive x (one per lane) x TV_TY rows x zc planes.  It walks
+// the item's planes in order and, in every plane, its rows in order, so what a voxel's divergence
+// needs from its neighbours is at hand: q_y of the row below from the previous row, q_z of the
+// plane below from the previous plane (one register per row), q_x of the voxel to the left from
+// lane - 1, u of the row above and of the plane above from the values loaded for them.  The
+// item's boundary values are recomputed: the row b0 - 1 in every plane, the plane c0 - 1 for
+// every row, and, for lane 0, q_x of the column a0 - 1 over all of the item's rows and planes
+// (before the walk, spread over the lanes).  Per voxel, one square root instead of four and two
+// loads instead of thirteen.
+constexpr int TV_TY = 8;       // rows per work item
+constexpr int TV_ZC_MAX = 16;  // planes per work item at most
+constexpr int TV_HXR = TV_TY * TV_ZC_MAX / 64;  // registers per lane for the left column's q_x
+
+struct TvItems {
+    int tx, ty, tz, zc;  // items along x (64 lanes each), y (TV_TY rows), z (zc planes)
+    __host__ __device__ long n() const { return (long)tx * ty * tz; }
+};
+
+// items of a volume: enough for about 4096 waves where the volume allows, zc in [4, 16]
+static TvItems tv_items(int nx, int ny, int nz) {
+    TvItems T;
+    T.tx = (nx + 63) / 64;
+    T.ty = (ny + TV_TY - 1) / TV_TY;
+    const long base = (long)T.tx * T.ty;
+    const long chunks = std::max(1L, (4096 + base - 1) / base);
+    int zc = (int)((nz + chunks - 1) / chunks);
+    zc = std::min(TV_ZC_MAX, std::max(zc, std::min(nz, 4)));
+    T.zc = zc;
+    T.tz = (nz + zc - 1) / zc;
+    return T;
+}
+
+// u(a+1, b, c) for every lane: lane + 1's value, and for lane 63 a load (0 outside the grid)
+__device__ __forceinline__ float x_next(float v, const float *__restrict__ u, long p, bool inside) {
+    float t = __shfl_down(v, 1, 64);
+    if ((threadIdx.x & 63) == 63) t = inside ? u[p + 1] : 0.0f;
+    return t;
+}
+
+// d = lambda N dR/du + (u - g)/t (g NULL: d = N dR/du) over the items w0, w0 + wstep, ...
+__device__ __forceinline__ void tv_grad_walk(const float *__restrict__ u, const float *__restrict__ g,
                                              float *__restrict__ d, const TVShape &k, float lambda, float inv_t,
-                                             double *__restrict__ partials, const Blk2 &B) {
-    __shared__ double sh[4];
+                                             const TvItems &T, int w0, int wstep, double &s_phi, double &s_fid,
+                                             double &s_d2) {
+    const int lane = threadIdx.x & 63;
     const long nxy = (long)k.nx * k.ny;
-    double s_phi = 0.0, s_fid = 0.0, s_d2 = 0.0;
-    const RowIter ri = row_iter(k, B);
-    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
-        const int c = row / k.ny, b = row - c * k.ny;
-        const long rbase = (long)c * nxy + (long)b * k.nx;
-        for (int a = ri.a0; a < k.nx; a += ri.astep) {
-            const long p = rbase + a;
-            float dx, dy, dz;
-            diffs(u, p, a, b, c, k, dx, dy, dz);
-            const float ph = phi_of(dx, dy, dz, k.eps2);
-            const float ip = __builtin_amdgcn_rcpf(ph);  // 1 ulp reciprocals instead of divisions
-            // the z difference of the last plane is identically 0 (reflective ghost): q_z = 0 there
-            float div = -(dx * ip * k.ihx + dy * ip * k.ihy + dz * ip * k.ihz);
-            if (a >= 1) {
-                float ex, ey, ez;
-                diffs(u, p - 1, a - 1, b, c, k, ex, ey, ez);
-                div += ex * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihx;
+    const int nw = (int)T.n();
+    for (int w = w0; w < nw; w += wstep) {
+        const int ix = w % T.tx, rest = w / T.tx;
+        const int iy = rest % T.ty, iz = rest / T.ty;
+        const int a = ix * 64 + lane, b0 = iy * TV_TY, c0 = iz * T.zc, c1 = min(k.nz, c0 + T.zc);
+        const bool ax = a < k.nx, ax1 = a + 1 < k.nx;
+        // u(a, b, c), 0 outside the grid
+        const auto ld = [&](int b, int c) -> float {
+            return (ax && b >= 0 && b < k.ny) ? u[(long)c * nxy + (long)b * k.nx + a] : 0.0f;
+        };
+        // u(a+1, b, c) from u(a, b, c) = v, 0 outside the grid
+        const auto xn = [&](float v, int b, int c) -> float {
+            const bool in = ax1 && b >= 0 && b < k.ny;
+            const float t = x_next(v, u, (long)c * nxy + (long)b * k.nx + a, in);
+            return in ? t : 0.0f;
+        };
+        float cu[TV_TY + 2];  // u of rows b0-1 .. b0+TV_TY at the current plane
+        float cz[TV_TY];      // q_z of rows b0 .. at the plane below
+#pragma unroll
+        for (int j = 0; j < TV_TY + 2; j++) cu[j] = ld(b0 - 1 + j, c0);
+        if (c0 > 0) {
+            float lo[TV_TY + 1];
+#pragma unroll
+            for (int j = 0; j <= TV_TY; j++) lo[j] = ld(b0 + j, c0 - 1);
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) {
+                const int b = b0 + j;
+                const float v0 = lo[j], vx = xn(v0, b, c0 - 1), vy = (b + 1 < k.ny) ? lo[j + 1] : 0.0f;
+                const float dx = (vx - v0) * k.ihx, dy = (vy - v0) * k.ihy, dz = (cu[j + 1] - v0) * k.ihz;
+                cz[j] = dz * __builtin_amdgcn_rcpf(phi_of(dx, dy, dz, k.eps2));
             }
-            if (b >= 1) {
-                float ex, ey, ez;
-                diffs(u, p - k.nx, a, b - 1, c, k, ex, ey, ez);
-                div += ey * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihy;
+        } else {
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) cz[j] = 0.0f;
+        }
+        // q_x of the column a0 - 1 for the item's rows and planes: point i = (c - c0) * TV_TY + (b - b0)
+        // in register i / 64 of lane i % 64
+        float hx[TV_HXR];
+#pragma unroll
+        for (int r = 0; r < TV_HXR; r++) {
+            hx[r] = 0.0f;
+            const int i = lane + 64 * r;
+            const int b = b0 + i % TV_TY, c = c0 + i / TV_TY;
+            if (ix > 0 && c < c1 && b < k.ny) {
+                const long p = (long)c * nxy + (long)b * k.nx + (ix * 64 - 1);
+                const float v0 = u[p], vx = u[p + 1];
+                const float vy = (b + 1 < k.ny) ? u[p + k.nx] : 0.0f;
+                const float vz = (c + 1 < k.nz) ? u[p + nxy] : v0;
+                const float dx = (vx - v0) * k.ihx, dy = (vy - v0) * k.ihy, dz = (vz - v0) * k.ihz;
+                hx[r] = dx * __builtin_amdgcn_rcpf(phi_of(dx, dy, dz, k.eps2));
             }
-            if (c >= 1) {
-                float ex, ey, ez;
-                diffs(u, p - nxy, a, b, c - 1, k, ex, ey, ez);
-                div += ez * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihz;
+        }
+        for (int c = c0; c < c1; c++) {
+            const bool zin = c + 1 < k.nz;
+            float nu[TV_TY + 2];  // u at the plane above (the last plane: its own values, dz = 0)
+#pragma unroll
+            for (int j = 0; j < TV_TY + 2; j++) nu[j] = zin ? ld(b0 - 1 + j, c + 1) : cu[j];
+            float gv[TV_TY];
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) {
+                const int b = b0 + j;
+                gv[j] = (g && ax && b < k.ny) ? g[(long)c * nxy + (long)b * k.nx + a] : 0.0f;
             }
-            float dv;
-            if (g) {
-                const float r = u[p] - g[p];
-                dv = fmaf(lambda, div, r * inv_t);
-                s_fid += (double)r * (double)r;
-            } else {
-                dv = div;
+            // q_y of the row below b0 (recomputed: it belongs to the item below)
+            float qy_prev = 0.0f;
+            if (b0 > 0) {
+                const int b = b0 - 1;
+                const float v0 = cu[0], vx = xn(v0, b, c), vy = cu[1];
+                const float dx = (vx - v0) * k.ihx, dy = (vy - v0) * k.ihy, dz = (nu[0] - v0) * k.ihz;
+                qy_prev = dy * __builtin_amdgcn_rcpf(phi_of(dx, dy, dz, k.eps2));
             }
-            d[p] = dv;
-            s_phi += (double)ph;
-            s_d2 += (double)dv * (double)dv;
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) {
+                const int b = b0 + j;
+                const float v0 = cu[j + 1], vx = xn(v0, b, c), vy = (b + 1 < k.ny) ? cu[j + 2] : 0.0f;
+                const float dx = (vx - v0) * k.ihx, dy = (vy - v0) * k.ihy, dz = (nu[j + 1] - v0) * k.ihz;
+                const float ph = phi_of(dx, dy, dz, k.eps2);
+                const float ip = __builtin_amdgcn_rcpf(ph);
+                const float qx = dx * ip, qy = dy * ip, qz = dz * ip;
+                float div = -(qx * k.ihx + qy * k.ihy + qz * k.ihz);
+                // q_x of the voxel to the left: lane - 1, or for lane 0 the recomputed column
+                float left = __shfl_up(qx, 1, 64);
+                const int i = (c - c0) * TV_TY + j;
+                float hsrc = hx[0];
+#pragma unroll
+                for (int r = 1; r < TV_HXR; r++)
+                    if ((i >> 6) == r) hsrc = hx[r];
+                const float hv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hsrc), i & 63));
+                if (lane == 0) left = hv;
+                if (a >= 1) div += left * k.ihx;
+                if (b >= 1) div += qy_prev * k.ihy;
+                if (c >= 1) div += cz[j] * k.ihz;
+                qy_prev = qy;
+                cz[j] = qz;
+                if (ax && b < k.ny) {
+                    float dv;
+                    if (g) {
+                        const float r = v0 - gv[j];
+                        dv = fmaf(lambda, div, r * inv_t);
+                        s_fid += (double)r * (double)r;
+                    } else {
+                        dv = div;
+                    }
+                    d[(long)c * nxy + (long)b * k.nx + a] = dv;
+                    s_phi += (double)ph;
+                    s_d2 += (double)dv * (double)dv;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < TV_TY + 2; j++) cu[j] = nu[j];
         }
     }
-    const int blk = B.by * B.gx + B.bx;
+}
+
+// trial energies E_R(u - s_m d), m < M, over the items w0, w0 + wstep, ...: per voxel the forward
+// differences of w = u - s_m d from the loaded u and d of the voxel, lane + 1, the row above (loaded
+// with the item's rows) and the plane above (loaded for the next plane)
+template <int M>
+__device__ __forceinline__ void tv_trial_walk(const float *__restrict__ u, const float *__restrict__ d,
+                                              const float *__restrict__ g, const TVShape &k, const float *s,
+                                              const TvItems &T, int w0, int wstep, double *s_phi, double *s_fid) {
+    const int lane = threadIdx.x & 63;
+    const long nxy = (long)k.nx * k.ny;
+    const int nw = (int)T.n();
+    for (int w = w0; w < nw; w += wstep) {
+        const int ix = w % T.tx, rest = w / T.tx;
+        const int iy = rest % T.ty, iz = rest / T.ty;
+        const int a = ix * 64 + lane, b0 = iy * TV_TY, c0 = iz * T.zc, c1 = min(k.nz, c0 + T.zc);
+        const bool ax = a < k.nx, ax1 = a + 1 < k.nx;
+        const auto ld = [&](const float *__restrict__ v, int b, int c) -> float {
+            return (ax && b < k.ny) ? v[(long)c * nxy + (long)b * k.nx + a] : 0.0f;
+        };
+        const auto xn = [&](const float *__restrict__ v, float val, int b, int c) -> float {
+            const bool in = ax1 && b < k.ny;
+            const float t = x_next(val, v, (long)c * nxy + (long)b * k.nx + a, in);
+            return in ? t : 0.0f;
+        };
+        float cu[TV_TY + 1], cd[TV_TY + 1];  // rows b0 .. b0+TV_TY at the current plane
+#pragma unroll
+        for (int j = 0; j <= TV_TY; j++) {
+            cu[j] = ld(u, b0 + j, c0);
+            cd[j] = ld(d, b0 + j, c0);
+        }
+        for (int c = c0; c < c1; c++) {
+            const bool zin = c + 1 < k.nz;
+            float nu[TV_TY + 1], nd[TV_TY + 1];
+#pragma unroll
+            for (int j = 0; j <= TV_TY; j++) {
+                nu[j] = zin ? ld(u, b0 + j, c + 1) : cu[j];
+                nd[j] = zin ? ld(d, b0 + j, c + 1) : cd[j];
+            }
+            float gv[TV_TY];
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) gv[j] = ld(g, b0 + j, c);
+#pragma unroll
+            for (int j = 0; j < TV_TY; j++) {
+                const int b = b0 + j;
+                const float ux = xn(u, cu[j], b, c), dxv = xn(d, cd[j], b, c);
+                const bool yin = b + 1 < k.ny;
+                if (ax && b < k.ny) {
+#pragma unroll
+                    for (int m = 0; m < M; m++) {
+                        const float w0v = fmaf(-s[m], cd[j], cu[j]);
+                        const float wx = fmaf(-s[m], dxv, ux);
+                        const float wy = yin ? fmaf(-s[m], cd[j + 1], cu[j + 1]) : 0.0f;
+                        const float wz = fmaf(-s[m], nd[j], nu[j]);
+                        const float r = w0v - gv[j];
+                        s_phi[m] += (double)phi_of((wx - w0v) * k.ihx, (wy - w0v) * k.ihy, (wz - w0v) * k.ihz,
+                                                   k.eps2);
+                        s_fid[m] += (double)r * (double)r;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j <= TV_TY; j++) {
+                cu[j] = nu[j];
+                cd[j] = nd[j];
+            }
+        }
+    }
+}
+
+// d = lambda * N dR/du + (u - g)/t (g may be NULL: then d = N dR/du and lambda is ignored) on work
+// group blk of nblk (4 waves, 4 items at a time).  partials[blk] = {sum phi, sum (u-g)^2, sum d^2}.
+__device__ __forceinline__ void tv_grad_body(const float *__restrict__ u, const float *__restrict__ g,
+                                             float *__restrict__ d, const TVShape &k, float lambda, float inv_t,
+                                             const TvItems &T, double *__restrict__ partials, int blk, int nblk) {
+    __shared__ double sh[4];
+    double s_phi = 0.0, s_fid = 0.0, s_d2 = 0.0;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    tv_grad_walk(u, g, d, k, lambda, inv_t, T, blk * 4 + wave, nblk * 4, s_phi, s_fid, s_d2);
     double v;
     v = block_sum(s_phi, sh);
     if (threadIdx.x == 0) partials[blk * 3 + 0] = v;
@@ -157,8 +347,8 @@ __device__ __forceinline__ void tv_grad_body(const float *__restrict__ u, const 
 
 __global__ void __launch_bounds__(256) k_tv_grad(const float *__restrict__ u, const float *__restrict__ g,
                                                  float *__restrict__ d, TVShape k, float lambda, float inv_t,
-                                                 double *__restrict__ partials) {
-    tv_grad_body(u, g, d, k, lambda, inv_t, partials, hw_blk2());
+                                                 TvItems T, double *__restrict__ partials) {
+    tv_grad_body(u, g, d, k, lambda, inv_t, T, partials, blockIdx.x, gridDim.x);
 }
 
 // sum phi only (energy of a volume)
@@ -181,13 +371,14 @@ __global__ void __launch_bounds__(256) k_tv_energy(const float *__restrict__ u, 
     if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
-// Trial energies at s_m = s0 * alpha^m, m < M.  partials[block][2m + {0,1}] = {sum phi, sum fid}.
+// Trial energies at s_m = s0 * alpha^m, m < M, on work group blk of nblk.
+// partials[blk][2m + {0,1}] = {sum phi, sum fid}.
 template <int M>
 __device__ __forceinline__ void tv_trial_body(const float *__restrict__ u, const float *__restrict__ d,
                                               const float *__restrict__ g, const TVShape &k, double t, double alpha,
-                                              int m0, double *__restrict__ partials, const Blk2 &B) {
+                                              int m0, const TvItems &T, double *__restrict__ partials, int blk,
+                                              int nblk) {
     __shared__ double sh[4];
-    const long nxy = (long)k.nx * k.ny;
     // s_m = t alpha^(m0 + m), formed exactly as the decision kernel forms it
     float s[M];
     double sd = t;
@@ -200,24 +391,8 @@ __device__ __forceinline__ void tv_trial_body(const float *__restrict__ u, const
     double s_phi[M], s_fid[M];
 #pragma unroll
     for (int m = 0; m < M; m++) s_phi[m] = s_fid[m] = 0.0;
-    const RowIter ri = row_iter(k, B);
-    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
-        const int c = row / k.ny, b = row - c * k.ny;
-        const long rbase = (long)c * nxy + (long)b * k.nx;
-        for (int a = ri.a0; a < k.nx; a += ri.astep) {
-            const long p = rbase + a;
-            const float gp = g[p];
-#pragma unroll
-            for (int m = 0; m < M; m++) {
-                float w0, dx, dy, dz;
-                diffs_step(u, d, s[m], p, a, b, c, k, w0, dx, dy, dz);
-                const float r = w0 - gp;
-                s_phi[m] += (double)phi_of(dx, dy, dz, k.eps2);
-                s_fid[m] += (double)r * (double)r;
-            }
-        }
-    }
-    const int blk = B.by * B.gx + B.bx;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    tv_trial_walk<M>(u, d, g, k, s, T, blk * 4 + wave, nblk * 4, s_phi, s_fid);
 #pragma unroll
     for (int m = 0; m < M; m++) {
         double v = block_sum(s_phi[m], sh);
@@ -230,8 +405,8 @@ __device__ __forceinline__ void tv_trial_body(const float *__restrict__ u, const
 template <int M>
 __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, const float *__restrict__ d,
                                                   const float *__restrict__ g, TVShape k, double t, double alpha,
-                                                  int m0, double *__restrict__ partials) {
-    tv_trial_body<M>(u, d, g, k, t, alpha, m0, partials, hw_blk2());
+                                                  int m0, TvItems T, double *__restrict__ partials) {
+    tv_trial_body<M>(u, d, g, k, t, alpha, m0, T, partials, blockIdx.x, gridDim.x);
 }
 
 // sum of `nb` rows of `width` partials: out[j] = sum_b part[b * width + j], in a fixed order
@@ -369,7 +544,7 @@ __device__ double small_block_sum(double v, double *sh) {
     return s;
 }
 
-__global__ void k_rof_small_init(RofSmallState *st, int replay_pos) {
+__global__ void k_rof_small_init(RofLog *st, int replay_pos) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->n_rec = 0;
         st->replay_pos = replay_pos;
@@ -381,7 +556,7 @@ __global__ void k_rof_small_init(RofSmallState *st, int replay_pos) {
 __global__ void __launch_bounds__(SMALL_THREADS)
     k_rof_small(float *__restrict__ u, const float *__restrict__ g, float *__restrict__ d, TVShape k, double lambda,
                 double t, double c_armijo, double alpha, double tol, int max_iter, int max_bt,
-                const int *__restrict__ replay, int replay_len, RofSmallState *__restrict__ st,
+                const int *__restrict__ replay, int replay_len, RofLog *__restrict__ st,
                 RofRecord *__restrict__ rec, int rec_cap, int level, int outer) {
     __shared__ double sh[SMALL_THREADS / 64];
     const long nxy = (long)k.nx * k.ny;
@@ -508,20 +683,180 @@ __global__ void __launch_bounds__(SMALL_THREADS)
 }
 
 
+// ---- Step 2 as flag-gated launch chains (larger volumes) -----------------------------------
+// The host enqueues whole steps ahead of the decisions: apply the last accepted step, a new
+// gradient, one trial window, the decision.  Each kernel reads the loop's state first and returns
+// at once when the loop has ended or the step does not need it, so the steps enqueued after the
+// loop's last decision cost a few microseconds each, and the device never waits for the host
+// between ROF iterations or backtracking windows.  The passes are the multi-kernel path's, and
+// the decision kernel forms the sums in k_sum_rows's order and decides with the same body, so the
+// results are bitwise those of a host-driven loop over the same kernels.
+__global__ void k_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, int init_state) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    RofGate g{};
+    g.run = 1;
+    g.grad = 1;
+    *gate = g;
+    if (init_state) {
+        st->n_rec = 0;
+        st->replay_pos = replay_pos;
+        st->status = 0;
+        st->pad = 0;
+    }
+}
+
+__global__ void k_axpy_gated(float *__restrict__ u, const float *__restrict__ d, const RofControl *__restrict__ ctl,
+                             const RofGate *__restrict__ gate, long n, int pending_only) {
+    const bool on = pending_only ? gate->pending != 0 : (gate->run != 0 && gate->apply != 0);
+    if (!on) return;
+    axpy_step_body(u, d, ctl, n, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) k_tv_grad_gated(const float *__restrict__ u, const float *__restrict__ g,
+                                                       float *__restrict__ d, TVShape k, float lambda, float inv_t,
+                                                       TvItems T, double *__restrict__ partials,
+                                                       const RofGate *__restrict__ gate) {
+    if (!gate->run || !gate->grad) return;
+    tv_grad_body(u, g, d, k, lambda, inv_t, T, partials, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) k_tv_trial_gated(const float *__restrict__ u, const float *__restrict__ d,
+                                                        const float *__restrict__ g, TVShape k, double t,
+                                                        double alpha, TvItems T, double *__restrict__ partials,
+                                                        const RofGate *__restrict__ gate) {
+    if (!gate->run) return;
+    const int m0 = gate->m0;
+    // the first window tries the full step only, later ones CBCT_TRIALS step sizes
+    if (m0 == 0) tv_trial_body<1>(u, d, g, k, t, alpha, 0, T, partials, blockIdx.x, gridDim.x);
+    else tv_trial_body<CBCT_TRIALS>(u, d, g, k, t, alpha, m0, T, partials, blockIdx.x, gridDim.x);
+}
+
+struct GateDecide {
+    const double *pg, *pt;  // gradient and trial partials
+    double *sums;
+    int nb;
+    double inv_n, lambda, t, c_armijo, alpha, tol;
+    int max_iter, max_bt;
+    RofControl *ctl;
+    RofGate *gate;
+    RofLog *st;
+    const int *replay;
+    int replay_len;
+    RofRecord *rec;
+    int rec_cap, level, outer;
+    int *mirror;
+    int seq;
+};
+
+// the decision of a gated step (one work-group of 256 threads): the fixed-order sums of the step's
+// passes, the Armijo decision, the loop's next state, the iteration's record, the host's word
+__device__ __forceinline__ void gate_decide_body(const GateDecide &A) {
+    __shared__ int run_s, grad_s, m0_s;
+    if (threadIdx.x == 0) {
+        run_s = A.gate->run;
+        grad_s = A.gate->grad;
+        m0_s = A.gate->m0;
+    }
+    __syncthreads();
+    if (!run_s) return;
+    const int M = m0_s == 0 ? 1 : CBCT_TRIALS;
+    if (grad_s) sum_rows_body(A.pg, A.nb, 3, A.sums);
+    __syncthreads();
+    sum_rows_body(A.pt, A.nb, 2 * M, A.sums + 3);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    RofGate G = *A.gate;
+    RofLog S = *A.st;
+    // the replayed decision of this ROF iteration, if any (applies to all of its windows)
+    int forced = -2, fend = -1;
+    if (A.replay && S.replay_pos < A.replay_len) {
+        forced = A.replay[2 * S.replay_pos];
+        fend = A.replay[2 * S.replay_pos + 1] != 0 ? 1 : 0;
+    }
+    RofControl c{};
+    if (forced == -1) {
+        // replayed: the search found no admissible step (the iteration's gradient sums only)
+        c.e0 = A.lambda * A.sums[0] * A.inv_n + A.sums[1] * A.inv_n / (2.0 * A.t);
+        c.G = A.sums[2] * A.inv_n;
+        c.accepted = -1;
+        *A.ctl = c;
+    } else {
+        rof_decide_body(A.sums, M, m0_s, forced, A.inv_n, A.lambda, A.t, A.c_armijo, A.alpha, A.max_bt, A.ctl,
+                        nullptr, 0);
+        c = *A.ctl;
+    }
+    if (c.accepted == 0 && c.next_m0 > m0_s) {
+        // the next window, same gradient
+        G.m0 = c.next_m0;
+        G.apply = 0;
+        G.grad = 0;
+    } else {
+        if (forced != -2) S.replay_pos++;
+        if (A.rec && S.n_rec < A.rec_cap) {
+            RofRecord R;
+            R.e0 = c.e0;
+            R.e_trial = c.e_trial;
+            R.G = c.G;
+            R.level = A.level;
+            R.outer = A.outer;
+            R.inner = G.it;
+            R.m = c.accepted == 1 ? c.m : -1;
+            A.rec[S.n_rec] = R;
+        }
+        S.n_rec++;
+        if (!isfinite(c.e0) || !isfinite(c.G)) {
+            S.status = 1;
+            G.run = 0;
+        } else if (c.accepted != 1) {
+            G.run = 0;  // Eq. 5 held for no step: keep u
+        } else {
+            const bool own_stop =
+                c.e0 == 0.0 || c.G == 0.0 || fabs(c.e_trial - c.e0) / c.e0 < A.tol;
+            const bool stop = (fend >= 0 ? fend == 1 : own_stop) || G.it + 1 == A.max_iter;
+            if (stop) {
+                G.run = 0;
+                G.pending = 1;
+            } else {
+                G.apply = 1;
+                G.grad = 1;
+                G.m0 = 0;
+                G.it++;
+            }
+        }
+    }
+    *A.gate = G;
+    *A.st = S;
+    if (A.mirror) {
+        __threadfence_system();
+        *reinterpret_cast<volatile int *>(A.mirror) = cbct_gate_word(A.seq, S.status, G.run);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rof_decide_gated(GateDecide A) { gate_decide_body(A); }
+
 // ---- batched kernels (serving engine) ------------------------------------------------------
-struct BTvItem {
-    const float *u, *g;
+// One gated step of several requests' Step 2 in shared launches: each request's work-groups run
+// the solo kernels' bodies on its buffers, grid and loop state (so its results are bitwise its
+// solo results), and a request whose loop has ended leaves its work-groups idle.
+struct BStepItem {
+    float *u;
+    const float *g;
     float *d;
-    double *partials, *out;
+    double *pg, *pt;  // gradient and trial partials
+    const RofControl *ctl;
+    const RofGate *gate;
     TVShape k;
     float lambda, inv_t;
     double t, alpha;
-    int m0, gx, gy;
+    TvItems T;
+    long n;
+    int nb, nba;  // TV work-groups, update work-groups
 };
-struct BTv {
+struct BStep {
     int n;
-    int wg0[CBCT_MAXB + 1];
-    BTvItem it[CBCT_MAXB];
+    int wg0[CBCT_MAXB + 1];  // exclusive prefix of the TV passes' work-groups
+    int wa0[CBCT_MAXB + 1];  // the same for the update pass
+    BStepItem it[CBCT_MAXB];
 };
 
 // the request a work-group of a batched launch belongs to (wg0: exclusive prefix of work-groups)
@@ -531,65 +866,57 @@ __device__ __forceinline__ int batch_of(const int *wg0, int n, int w) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_tv_grad_b(BTv B) {
-    const int r = batch_of(B.wg0, B.n, blockIdx.x);
-    const BTvItem &it = B.it[r];
-    const int local = blockIdx.x - B.wg0[r];
-    tv_grad_body(it.u, it.g, it.d, it.k, it.lambda, it.inv_t, it.partials,
-                 Blk2{local % it.gx, local / it.gx, it.gx, it.gy});
+__global__ void k_axpy_gated_b(BStep B) {
+    const int r = batch_of(B.wa0, B.n, blockIdx.x);
+    const BStepItem &it = B.it[r];
+    if (!it.gate->run || !it.gate->apply) return;
+    axpy_step_body(it.u, it.d, it.ctl, it.n, blockIdx.x - B.wa0[r], it.nba);
 }
 
-template <int M>
-__global__ void __launch_bounds__(256) k_tv_trial_b(BTv B) {
+__global__ void __launch_bounds__(256) k_tv_grad_gated_b(BStep B) {
     const int r = batch_of(B.wg0, B.n, blockIdx.x);
-    const BTvItem &it = B.it[r];
-    const int local = blockIdx.x - B.wg0[r];
-    tv_trial_body<M>(it.u, it.d, it.g, it.k, it.t, it.alpha, it.m0, it.partials,
-                     Blk2{local % it.gx, local / it.gx, it.gx, it.gy});
+    const BStepItem &it = B.it[r];
+    if (!it.gate->run || !it.gate->grad) return;
+    tv_grad_body(it.u, it.g, it.d, it.k, it.lambda, it.inv_t, it.T, it.pg, blockIdx.x - B.wg0[r], it.nb);
 }
+
+__global__ void __launch_bounds__(256) k_tv_trial_gated_b(BStep B) {
+    const int r = batch_of(B.wg0, B.n, blockIdx.x);
+    const BStepItem &it = B.it[r];
+    if (!it.gate->run) return;
+    const int m0 = it.gate->m0, local = blockIdx.x - B.wg0[r];
+    if (m0 == 0) tv_trial_body<1>(it.u, it.d, it.g, it.k, it.t, it.alpha, 0, it.T, it.pt, local, it.nb);
+    else tv_trial_body<CBCT_TRIALS>(it.u, it.d, it.g, it.k, it.t, it.alpha, m0, it.T, it.pt, local, it.nb);
+}
+
+struct BDecide {
+    int n;
+    GateDecide it[CBCT_MAXB];
+};
 
 // one work-group per request
-__global__ void __launch_bounds__(256) k_sum_rows_b(BTv B, int width) {
-    const BTvItem &it = B.it[blockIdx.x];
-    sum_rows_body(it.partials, it.gx * it.gy, width, it.out);
-}
+__global__ void __launch_bounds__(256) k_rof_decide_gated_b(BDecide B) { gate_decide_body(B.it[blockIdx.x]); }
 
-struct BDecItem {
-    const double *sums;
-    int m0, M, max_bt, seq;
-    double inv_n, lambda, t, c_armijo, alpha;
-    RofControl *ctl, *mirror;
-};
-struct BDec {
-    int n;
-    BDecItem it[CBCT_MAXB];
+struct BInit {
+    int n, init_state;
+    RofGate *gate[CBCT_MAXB];
+    RofLog *st[CBCT_MAXB];
 };
 
-__global__ void k_rof_decide_b(BDec B) {
+__global__ void k_rof_gate_init_b(BInit B) {
     const int r = threadIdx.x;
     if (blockIdx.x != 0 || r >= B.n) return;
-    const BDecItem &it = B.it[r];
-    rof_decide_body(it.sums, it.M, it.m0, -1, it.inv_n, it.lambda, it.t, it.c_armijo, it.alpha, it.max_bt, it.ctl,
-                    it.mirror, it.seq);
-}
-
-struct BAxItem {
-    float *u;
-    const float *d;
-    const RofControl *ctl;
-    long n;
-    int nb;
-};
-struct BAx {
-    int n;
-    int wg0[CBCT_MAXB + 1];
-    BAxItem it[CBCT_MAXB];
-};
-
-__global__ void k_axpy_b(BAx B) {
-    const int r = batch_of(B.wg0, B.n, blockIdx.x);
-    const BAxItem &it = B.it[r];
-    axpy_step_body(it.u, it.d, it.ctl, it.n, blockIdx.x - B.wg0[r], it.nb);
+    RofGate g{};
+    g.run = 1;
+    g.grad = 1;
+    *B.gate[r] = g;
+    if (B.init_state) {
+        RofLog *st = B.st[r];
+        st->n_rec = 0;
+        st->replay_pos = 0;
+        st->status = 0;
+        st->pad = 0;
+    }
 }
 
 }  // namespace
@@ -600,8 +927,8 @@ static TVShape tv_shape(const Level &L, double eps) {
                    (float)(eps * eps)};
 }
 
-// fixed reduction grid of a volume: (x segments of 64) x (row groups of 4), about
-// CBCT_RED_BLOCKS work-groups
+// grid of the energy pass: (x segments of 64) x (row groups of 4), about CBCT_RED_BLOCKS
+// work-groups
 static dim3 tv_grid(const Level &L) {
     const int gx = (L.nx + 63) / 64;
     const int rows = (L.ny * L.nz + 3) / 4;
@@ -609,9 +936,15 @@ static dim3 tv_grid(const Level &L) {
     return dim3(gx, gy);
 }
 
+// work-groups of the tiled gradient and trial passes (4 items at a time; fixed by the shape, so
+// the partial-sum layout is too)
+static int tv_blocks(const TvItems &T) {
+    return (int)std::min<long>((T.n() + 3) / 4, CBCT_RED_BLOCKS);
+}
+
 int cbct_reduce_blocks(const Level &L) {
     const dim3 g = tv_grid(L);
-    return (int)(g.x * g.y);
+    return std::max((int)(g.x * g.y), tv_blocks(tv_items(L.nx, L.ny, L.nz)));
 }
 
 #define LAUNCH_CHECK(what)                                  \
@@ -622,9 +955,10 @@ int cbct_reduce_blocks(const Level &L) {
 
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L);
-    hipLaunchKernelGGL(k_tv_grad, tv_grid(L), dim3(256), 0, s, u, g, d, tv_shape(L, eps), (float)lambda,
-                       (float)(1.0 / t), partials);
+    const TvItems T = tv_items(L.nx, L.ny, L.nz);
+    const int nb = tv_blocks(T);
+    hipLaunchKernelGGL(k_tv_grad, dim3(nb), dim3(256), 0, s, u, g, d, tv_shape(L, eps), (float)lambda,
+                       (float)(1.0 / t), T, partials);
     LAUNCH_CHECK("k_tv_grad");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 3, sums);
     LAUNCH_CHECK("k_sum_rows");
@@ -633,8 +967,9 @@ cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, cons
 
 cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, double *partials, double *sum,
                                   hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L);
-    hipLaunchKernelGGL(k_tv_energy, tv_grid(L), dim3(256), 0, s, u, tv_shape(L, eps), partials);
+    const dim3 gr = tv_grid(L);
+    const int nb = (int)(gr.x * gr.y);
+    hipLaunchKernelGGL(k_tv_energy, gr, dim3(256), 0, s, u, tv_shape(L, eps), partials);
     LAUNCH_CHECK("k_tv_energy");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 1, sum);
     LAUNCH_CHECK("k_sum_rows");
@@ -643,13 +978,14 @@ cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, do
 
 cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, const float *d, const float *g,
                                  double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s) {
-    const int nb = cbct_reduce_blocks(L);
+    const TvItems T = tv_items(L.nx, L.ny, L.nz);
+    const int nb = tv_blocks(T);
     if (M == 1)
-        hipLaunchKernelGGL((k_tv_trial<1>), tv_grid(L), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha, m0,
+        hipLaunchKernelGGL((k_tv_trial<1>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha, m0, T,
                            partials);
     else
-        hipLaunchKernelGGL((k_tv_trial<CBCT_TRIALS>), tv_grid(L), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t,
-                           alpha, m0, partials);
+        hipLaunchKernelGGL((k_tv_trial<CBCT_TRIALS>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t,
+                           alpha, m0, T, partials);
     LAUNCH_CHECK("k_tv_trial");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 2 * (M == 1 ? 1 : CBCT_TRIALS), sums);
     LAUNCH_CHECK("k_sum_rows");
@@ -681,7 +1017,7 @@ cbct_status cbct_launch_sum_rows(const double *part, int nb, int width, double *
 
 cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const float *g, float *d, double lambda,
                                   double t, double c_armijo, double alpha, double tol, int max_iter, int max_bt,
-                                  const int *replay, int replay_len, int replay_pos, RofSmallState *st,
+                                  const int *replay, int replay_len, int replay_pos, RofLog *st,
                                   RofRecord *rec, int rec_cap, int level, int outer, bool init, hipStream_t s) {
     if (init) {
         hipLaunchKernelGGL(k_rof_small_init, dim3(1), dim3(64), 0, s, st, replay_pos);
@@ -693,93 +1029,130 @@ cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const fl
     return CBCT_OK;
 }
 
+cbct_status cbct_launch_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, bool init_state,
+                                      hipStream_t s) {
+    hipLaunchKernelGGL(k_rof_gate_init, dim3(1), dim3(64), 0, s, gate, st, replay_pos, init_state ? 1 : 0);
+    LAUNCH_CHECK("k_rof_gate_init");
+    return CBCT_OK;
+}
+
+static GateDecide gate_decide_args(const Level &L, const RofStepArgs &a, int nb) {
+    GateDecide D;
+    D.pg = a.part;
+    D.pt = a.part + 3 * (size_t)CBCT_RED_BLOCKS;
+    D.sums = a.sums;
+    D.nb = nb;
+    D.inv_n = 1.0 / (double)L.nvox();
+    D.lambda = a.lambda;
+    D.t = a.t;
+    D.c_armijo = a.c_armijo;
+    D.alpha = a.alpha;
+    D.tol = a.tol;
+    D.max_iter = a.max_iter;
+    D.max_bt = a.max_bt;
+    D.ctl = a.ctl;
+    D.gate = a.gate;
+    D.st = a.st;
+    D.replay = a.replay;
+    D.replay_len = a.replay_len;
+    D.rec = a.rec;
+    D.rec_cap = a.rec_cap;
+    D.level = a.level;
+    D.outer = a.outer;
+    D.mirror = a.mirror;
+    D.seq = a.seq & CBCT_GATE_SEQ_MASK;
+    return D;
+}
+
+cbct_status cbct_launch_rof_step_gated(const Level &L, const RofStepArgs &a, hipStream_t s) {
+    const long n = L.nvox();
+    const int nba = (int)std::min<long>((n + 255) / 256, 4096);
+    const TvItems T = tv_items(L.nx, L.ny, L.nz);
+    const int nb = tv_blocks(T);
+    const TVShape k = tv_shape(L, a.eps);
+    double *pt = a.part + 3 * (size_t)CBCT_RED_BLOCKS;
+    hipLaunchKernelGGL(k_axpy_gated, dim3(nba), dim3(256), 0, s, a.u, a.d, a.ctl, a.gate, n, 0);
+    LAUNCH_CHECK("k_axpy_gated");
+    hipLaunchKernelGGL(k_tv_grad_gated, dim3(nb), dim3(256), 0, s, a.u, a.g, a.d, k, (float)a.lambda,
+                       (float)(1.0 / a.t), T, a.part, a.gate);
+    LAUNCH_CHECK("k_tv_grad_gated");
+    hipLaunchKernelGGL(k_tv_trial_gated, dim3(nb), dim3(256), 0, s, a.u, a.d, a.g, k, a.t, a.alpha, T, pt, a.gate);
+    LAUNCH_CHECK("k_tv_trial_gated");
+    const GateDecide D = gate_decide_args(L, a, nb);
+    hipLaunchKernelGGL(k_rof_decide_gated, dim3(1), dim3(256), 0, s, D);
+    LAUNCH_CHECK("k_rof_decide_gated");
+    return CBCT_OK;
+}
+
+cbct_status cbct_launch_axpy_pending(float *u, const float *d, const RofControl *ctl, const RofGate *gate, long n,
+                                     hipStream_t s) {
+    const int nb = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_axpy_gated, dim3(nb), dim3(256), 0, s, u, d, ctl, gate, n, 1);
+    LAUNCH_CHECK("k_axpy_gated");
+    return CBCT_OK;
+}
+
 // ---- batched launchers ---------------------------------------------------------------------
-static BTv make_btv(const TvReq *r, int n, int sums_off) {
-    BTv B{};
-    B.n = n;
-    int w = 0;
-    for (int q = 0; q < n; q++) {
-        const Level &L = *r[q].L;
-        const dim3 gr = tv_grid(L);
-        BTvItem &it = B.it[q];
-        it.u = r[q].u;
-        it.g = r[q].g;
-        it.d = r[q].d;
-        it.partials = r[q].partials;
-        it.out = r[q].sums + sums_off;
-        it.k = tv_shape(L, r[q].eps);
-        it.lambda = (float)r[q].lambda;
-        it.inv_t = (float)(1.0 / r[q].t);
-        it.t = r[q].t;
-        it.alpha = r[q].alpha;
-        it.m0 = r[q].m0;
-        it.gx = (int)gr.x;
-        it.gy = (int)gr.y;
-        B.wg0[q] = w;
-        w += it.gx * it.gy;
-    }
-    B.wg0[n] = w;
-    return B;
-}
-
-cbct_status cbct_launch_tv_grad_batch(const TvReq *r, int n, hipStream_t s) {
+cbct_status cbct_launch_rof_gate_init_batch(RofGate *const *gate, RofLog *const *st, int n, bool init_state,
+                                            hipStream_t s) {
     for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
         const int m = std::min(CBCT_MAXB, n - q0);
-        const BTv B = make_btv(r + q0, m, 0);
-        hipLaunchKernelGGL(k_tv_grad_b, dim3(B.wg0[m]), dim3(256), 0, s, B);
-        LAUNCH_CHECK("k_tv_grad_b");
-        hipLaunchKernelGGL(k_sum_rows_b, dim3(m), dim3(256), 0, s, B, 3);
-        LAUNCH_CHECK("k_sum_rows_b");
-    }
-    return CBCT_OK;
-}
-
-cbct_status cbct_launch_tv_trial_batch(const TvReq *r, int n, int M, hipStream_t s) {
-    if (M != 1 && M != CBCT_TRIALS) return cbct_set_error(CBCT_ERR_INTERNAL, "tv_trial_batch: M = %d", M);
-    for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
-        const int m = std::min(CBCT_MAXB, n - q0);
-        const BTv B = make_btv(r + q0, m, 3);
-        if (M == 1) hipLaunchKernelGGL((k_tv_trial_b<1>), dim3(B.wg0[m]), dim3(256), 0, s, B);
-        else hipLaunchKernelGGL((k_tv_trial_b<CBCT_TRIALS>), dim3(B.wg0[m]), dim3(256), 0, s, B);
-        LAUNCH_CHECK("k_tv_trial_b");
-        hipLaunchKernelGGL(k_sum_rows_b, dim3(m), dim3(256), 0, s, B, 2 * M);
-        LAUNCH_CHECK("k_sum_rows_b");
-    }
-    return CBCT_OK;
-}
-
-cbct_status cbct_launch_rof_decide_batch(const DecideReq *r, int n, hipStream_t s) {
-    for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
-        const int m = std::min(CBCT_MAXB, n - q0);
-        BDec B{};
+        BInit B{};
         B.n = m;
+        B.init_state = init_state ? 1 : 0;
         for (int q = 0; q < m; q++) {
-            const DecideReq &d = r[q0 + q];
-            B.it[q] = BDecItem{d.sums, d.m0, d.M, d.max_bt, d.seq, 1.0 / (double)d.nvox, d.lambda, d.t,
-                               d.c_armijo, d.alpha, d.ctl, d.mirror};
+            B.gate[q] = gate[q0 + q];
+            B.st[q] = st[q0 + q];
         }
-        hipLaunchKernelGGL(k_rof_decide_b, dim3(1), dim3(64), 0, s, B);
-        LAUNCH_CHECK("k_rof_decide_b");
+        hipLaunchKernelGGL(k_rof_gate_init_b, dim3(1), dim3(64), 0, s, B);
+        LAUNCH_CHECK("k_rof_gate_init_b");
     }
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_axpy_batch(const AxpyReq *r, int n, hipStream_t s) {
+cbct_status cbct_launch_rof_step_gated_batch(const Level *const *L, const RofStepArgs *a, int n, hipStream_t s) {
     for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
         const int m = std::min(CBCT_MAXB, n - q0);
-        BAx B{};
-        B.n = m;
-        int w = 0;
+        BStep B{};
+        BDecide D{};
+        B.n = D.n = m;
+        int w = 0, wa = 0;
         for (int q = 0; q < m; q++) {
-            const AxpyReq &a = r[q0 + q];
-            const int nb = (int)std::min<long>((a.n + 255) / 256, 4096);
-            B.it[q] = BAxItem{a.u, a.d, a.ctl, a.n, nb};
+            const Level &Lq = *L[q0 + q];
+            const RofStepArgs &aq = a[q0 + q];
+            BStepItem &it = B.it[q];
+            it.u = aq.u;
+            it.g = aq.g;
+            it.d = aq.d;
+            it.pg = aq.part;
+            it.pt = aq.part + 3 * (size_t)CBCT_RED_BLOCKS;
+            it.ctl = aq.ctl;
+            it.gate = aq.gate;
+            it.k = tv_shape(Lq, aq.eps);
+            it.lambda = (float)aq.lambda;
+            it.inv_t = (float)(1.0 / aq.t);
+            it.t = aq.t;
+            it.alpha = aq.alpha;
+            it.T = tv_items(Lq.nx, Lq.ny, Lq.nz);
+            it.n = Lq.nvox();
+            it.nb = tv_blocks(it.T);
+            it.nba = (int)std::min<long>((it.n + 255) / 256, 4096);
             B.wg0[q] = w;
-            w += nb;
+            B.wa0[q] = wa;
+            w += it.nb;
+            wa += it.nba;
+            D.it[q] = gate_decide_args(Lq, aq, it.nb);
         }
         B.wg0[m] = w;
-        hipLaunchKernelGGL(k_axpy_b, dim3(w), dim3(256), 0, s, B);
-        LAUNCH_CHECK("k_axpy_b");
+        B.wa0[m] = wa;
+        hipLaunchKernelGGL(k_axpy_gated_b, dim3(wa), dim3(256), 0, s, B);
+        LAUNCH_CHECK("k_axpy_gated_b");
+        hipLaunchKernelGGL(k_tv_grad_gated_b, dim3(w), dim3(256), 0, s, B);
+        LAUNCH_CHECK("k_tv_grad_gated_b");
+        hipLaunchKernelGGL(k_tv_trial_gated_b, dim3(w), dim3(256), 0, s, B);
+        LAUNCH_CHECK("k_tv_trial_gated_b");
+        hipLaunchKernelGGL(k_rof_decide_gated_b, dim3(m), dim3(256), 0, s, D);
+        LAUNCH_CHECK("k_rof_decide_gated_b");
     }
     return CBCT_OK;
 }

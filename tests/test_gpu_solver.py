@@ -82,6 +82,24 @@ def test_rof_alone_matches_oracle():
         assert rel_l2(to_np(u), res.f) < 1e-5, t
 
 
+def test_gated_loop_equals_host_driven_loop():
+    """Step 2 as gated launch chains (the device decides and the passes read its state) against
+    the host-driven loop over the same kernels (forced here by replaying the gated loop's own
+    decisions): the same volume bitwise, the same decision trace and energies."""
+    g = dataclasses.replace(G1, nx=40, ny=24, nz=16)  # above the one-work-group size
+    plan = _plan(g)
+    gv = 0.02 * S.random_volume(g, 12)
+    for t in (2.0, 8.6e-5):
+        announce("gated vs host-driven Step 2, t = %g" % t)
+        u1, st1 = plan.tv_prox(to_gpu(gv), 0.05, t)
+        u2, st2 = plan.tv_prox(to_gpu(gv), 0.05, t, replay=replay_records(st1["trace"]))
+        torch.cuda.synchronize()
+        assert len(st1["trace"]) > 0
+        assert [tuple(r) for r in st1["trace"]] == [tuple(r) for r in st2["trace"]], t
+        assert np.array_equal(st1["rof_e"], st2["rof_e"]), t
+        assert torch.equal(u1, u2), t
+
+
 # A decision that differs from the oracle's is an FP32 tie only when the oracle's own margin at it
 # is below this (relative to E_0): the GPU's energies are FP64 sums of FP32 values, within about
 # 1e-7 relative of the oracle's on the same decision sequence, so a genuine tie sits an order of
