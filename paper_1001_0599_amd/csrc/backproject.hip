@@ -97,9 +97,12 @@ template <int TZ, bool VEC>
 __global__ void __launch_bounds__(256)
     k_adj_gather(const float *__restrict__ Z, const ZIndex *__restrict__ zix, const ColParams *__restrict__ cols,
                  const ViewParams *__restrict__ views, AdjArgs A, const float *__restrict__ fbase, float kappa,
-                 float *__restrict__ out) {
-    int tx, ty, tz;
-    tile_of(tx, ty, tz);
+                 float *__restrict__ out, int vgroups, int vper, float *__restrict__ part) {
+    int tx, ty, tzg;
+    tile_of(tx, ty, tzg);
+    // view group g covers views [g vper, (g+1) vper) and writes part[g] (summed by k_adj_combine)
+    const int nzt = (A.nz + TZ - 1) / TZ, tz = tzg % nzt, grp = tzg / nzt;
+    const int v_begin = grp * vper, v_end = min(A.nviews, v_begin + vper);
     const int tid = threadIdx.x;
     const int a = tx * ADJ_TX + tid % ADJ_TX, b = ty * ADJ_TY + tid / ADJ_TX;
     const int c0 = tz * TZ;
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int q = 0; q < TZ; q++) acc[q] = 0.0f;
 
-    for (int view = 0; view < A.nviews; view++) {
+    for (int view = v_begin; view < v_end; view++) {
         const ViewParams vp = views[view];
         // detector columns whose samples can reach this voxel column: the footprint of its
         // support square (centre +- one voxel), widened by one column
@@ -161,12 +164,14 @@ __global__ void __launch_bounds__(256)
             }
         }
     }
+    const long nvox = (long)A.nx * A.ny * A.nz;
 #pragma unroll
     for (int q = 0; q < TZ; q++) {
         const int c = c0 + q;
         if (c < A.nz) {
             const long idx = ((long)c * A.ny + b) * A.nx + a;
-            out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
+            if (vgroups > 1) part[grp * nvox + idx] = acc[q];
+            else out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
         }
     }
 }
@@ -391,14 +396,15 @@ __global__ void __launch_bounds__(256) k_adj_combine(const float *__restrict__ p
     } while (0)
 
 template <int TZ>
-cbct_status launch_gather(const Level &L, const float *Z, const float *fbase, float kappa, float *out, hipStream_t s) {
-    dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (L.nz + TZ - 1) / TZ);
+cbct_status launch_gather(const Level &L, const float *Z, const float *fbase, float kappa, float *out, int vg,
+                          int vper, float *part, hipStream_t s) {
+    dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, ((L.nz + TZ - 1) / TZ) * vg);
     if (L.nz % TZ == 0)
         hipLaunchKernelGGL((k_adj_gather<TZ, true>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Z, L.d_zix, L.d_cols,
-                           L.d_views, L.adj, fbase, kappa, out);
+                           L.d_views, L.adj, fbase, kappa, out, vg, vper, part);
     else
         hipLaunchKernelGGL((k_adj_gather<TZ, false>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Z, L.d_zix, L.d_cols,
-                           L.d_views, L.adj, fbase, kappa, out);
+                           L.d_views, L.adj, fbase, kappa, out, vg, vper, part);
     LAUNCH_CHECK("k_adj_gather");
     return CBCT_OK;
 }
@@ -446,18 +452,22 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
         return copy_out2();
     }
     // other depths: per-lane gather, z cells per thread up to 64 (the window and weight work per
-    // voxel column and view is shared by all its cells)
-    int tz;
-    if (nz % 64 == 0) tz = 64;
-    else if (nz % 32 == 0) tz = 32;
-    else if (nz % 16 == 0) tz = 16;
-    else if (nz % 8 == 0) tz = 8;
-    else tz = nz > 32 ? 64 : nz > 16 ? 32 : nz > 8 ? 16 : 8;  // partial last tile, scalar loads
-    switch (tz) {
-        case 64: st = launch_gather<64>(L, Zws, fbase, kappa, out, s); break;
-        case 32: st = launch_gather<32>(L, Zws, fbase, kappa, out, s); break;
-        case 16: st = launch_gather<16>(L, Zws, fbase, kappa, out, s); break;
-        default: st = launch_gather<8>(L, Zws, fbase, kappa, out, s); break;
+    // voxel column and view is shared by all its cells), views split into groups on small grids
+    const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
+    float *part = Zws + L.adj_part_off;
+    switch (cbct_adj_lane_tz(nz)) {
+        case 64: st = launch_gather<64>(L, Zws, fbase, kappa, out, vg, vper, part, s); break;
+        case 32: st = launch_gather<32>(L, Zws, fbase, kappa, out, vg, vper, part, s); break;
+        case 16: st = launch_gather<16>(L, Zws, fbase, kappa, out, vg, vper, part, s); break;
+        default: st = launch_gather<8>(L, Zws, fbase, kappa, out, vg, vper, part, s); break;
     }
-    return st ? st : copy_out2();
+    if (st) return st;
+    if (vg > 1) {
+        const long n = L.nvox();
+        const int nb = (int)std::min<long>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out, out2);
+        LAUNCH_CHECK("k_adj_combine");
+        return CBCT_OK;
+    }
+    return copy_out2();
 }

@@ -62,9 +62,27 @@ inline int cbct_adj_staged_tz(int nz) { return nz % 32 == 0 ? 32 : 0; }
 // ones at least two groups: at 512x512x64 / 40 views two groups of 20 views (4096 work-groups,
 // shorter ones, and a shorter tail) measured 1.79 against 1.94 ms per P^T including the sum.
 
+// z cells per thread of the per-lane gather (depths that are not a multiple of 32)
+inline int cbct_adj_lane_tz(int nz) {
+    if (nz % 64 == 0) return 64;
+    if (nz % 32 == 0) return 32;
+    if (nz % 16 == 0) return 16;
+    if (nz % 8 == 0) return 8;
+    return nz > 32 ? 64 : nz > 16 ? 32 : nz > 8 ? 16 : 8;  // partial last tile, scalar loads
+}
+
+// The per-lane gather splits the views of small grids the same way, so that a grid of a few
+// tiles still spreads over the GPU: a 16^3 volume runs 16 work-groups of one view each instead
+// of one work-group walking all views.
 inline int cbct_adj_vsplit(int nx, int ny, int nz, int nviews) {
     const int tz = cbct_adj_staged_tz(nz);
-    if (!tz) return 1;
+    if (!tz) {
+        const int ltz = cbct_adj_lane_tz(nz);
+        const long tiles = (long)((nx + 15) / 16) * ((ny + 15) / 16) * ((nz + ltz - 1) / ltz);
+        long vs = 256 / std::max(tiles, 1L);
+        vs = std::min(vs, std::min<long>(16, nviews));
+        return (int)std::max(vs, 1L);
+    }
     const long tiles = (long)((nx + 15) / 16) * ((ny + 15) / 16) * (nz / tz);
     long vs = std::max(2048 / std::max(tiles, 1L), 2L);
     vs = std::min(vs, std::min<long>(16, nviews));
@@ -92,7 +110,7 @@ struct Level {
     AdjArgs adj;
     long z_floats = 0;            // size of the adjoint workspace (profiles + view-group partials)
     int zk_max = 0;               // most samples of one column inside the grid's support
-    int adj_vsplit = 1;           // view groups of the staged gather
+    int adj_vsplit = 1;           // view groups of the adjoint gather
     long adj_part_off = 0;        // float offset of the view-group partial volumes
     ZIndex *d_zix = nullptr;      // [nviews][nu]
     double schur_t = 0.0;         // cached Schur-bound step of the trilinear pair (0: not computed yet)
@@ -246,6 +264,7 @@ struct RofStepArgs {
     int rec_cap, level, outer;
     int *mirror;  // host-mapped word (device address), or NULL
     int seq;
+    int first;    // the loop's first step: no accepted step can be pending, the update is not launched
 };
 // resets the gate for a new loop; with init_state also the records and replay position
 cbct_status cbct_launch_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, bool init_state,

@@ -534,13 +534,15 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
                     a.outer = r->k;
                     a.mirror = s->mirror_dev ? &s->mirror_dev[r->slot].pad : nullptr;
                     a.seq = (s->seq.fetch_add(1) + 1) & CBCT_GATE_SEQ_MASK;
+                    a.first = issued == 0 ? 1 : 0;
                     r->seqs.push_back(a.seq);
                     lv.push_back(&L);
                     args.push_back(a);
                 }
                 if ((st = cbct_launch_rof_step_gated_batch(lv.data(), args.data(), (int)args.size(), st_))) return st;
-                s->batched_launches += 4;
-                s->batched_items += 4 * args.size();
+                const int nl = issued == 0 ? 3 : 4;  // the first step launches no update
+                s->batched_launches += nl;
+                s->batched_items += nl * args.size();
                 issued++;
             }
             if (known >= issued) break;  // every step a loop can take has run

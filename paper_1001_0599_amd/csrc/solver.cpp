@@ -392,6 +392,7 @@ cbct_status rof_loop_gated(const Level &L, const cbct_solve_params *pr, double t
     for (;;) {
         while ((long)seqs.size() < max_steps && (long)seqs.size() < known + AHEAD) {
             a.seq = next_seq();
+            a.first = seqs.empty() ? 1 : 0;
             seqs.push_back(a.seq);
             if ((st = cbct_launch_rof_step_gated(L, a, s))) return st;
         }

@@ -1071,8 +1071,10 @@ cbct_status cbct_launch_rof_step_gated(const Level &L, const RofStepArgs &a, hip
     const int nb = tv_blocks(T);
     const TVShape k = tv_shape(L, a.eps);
     double *pt = a.part + 3 * (size_t)CBCT_RED_BLOCKS;
-    hipLaunchKernelGGL(k_axpy_gated, dim3(nba), dim3(256), 0, s, a.u, a.d, a.ctl, a.gate, n, 0);
-    LAUNCH_CHECK("k_axpy_gated");
+    if (!a.first) {
+        hipLaunchKernelGGL(k_axpy_gated, dim3(nba), dim3(256), 0, s, a.u, a.d, a.ctl, a.gate, n, 0);
+        LAUNCH_CHECK("k_axpy_gated");
+    }
     hipLaunchKernelGGL(k_tv_grad_gated, dim3(nb), dim3(256), 0, s, a.u, a.g, a.d, k, (float)a.lambda,
                        (float)(1.0 / a.t), T, a.part, a.gate);
     LAUNCH_CHECK("k_tv_grad_gated");
@@ -1145,8 +1147,10 @@ cbct_status cbct_launch_rof_step_gated_batch(const Level *const *L, const RofSte
         }
         B.wg0[m] = w;
         B.wa0[m] = wa;
-        hipLaunchKernelGGL(k_axpy_gated_b, dim3(wa), dim3(256), 0, s, B);
-        LAUNCH_CHECK("k_axpy_gated_b");
+        if (!a[q0].first) {  // the steps of one batch are all first steps or none is
+            hipLaunchKernelGGL(k_axpy_gated_b, dim3(wa), dim3(256), 0, s, B);
+            LAUNCH_CHECK("k_axpy_gated_b");
+        }
         hipLaunchKernelGGL(k_tv_grad_gated_b, dim3(w), dim3(256), 0, s, B);
         LAUNCH_CHECK("k_tv_grad_gated_b");
         hipLaunchKernelGGL(k_tv_trial_gated_b, dim3(w), dim3(256), 0, s, B);
