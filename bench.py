@@ -30,7 +30,7 @@ def log(msg):
 # TCC_MISS).  The record names the sources it was measured on; it is reported only while they are
 # unchanged.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "adjoint_traffic_512x512x64_40views.txt")
-TRAFFIC_SOURCES = ["backproject.hip", "adj_profiles.h", "cbct_internal.h", "plan.cpp"]
+TRAFFIC_SOURCES = ["backproject.hip", "adj_profiles.h", "geometry_tables.h", "plan.cpp"]
 
 
 def sources_digest(names):

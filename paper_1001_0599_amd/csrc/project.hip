@@ -232,7 +232,9 @@ __device__ __forceinline__ float ldv(__amdgpu_buffer_rsrc_t r, int off, int, int
 // leaving the slab read zeros.
 template <int KC>
 __host__ __device__ constexpr size_t runs_lds_bytes(int nz, int nwaves) {
-    return ((size_t)(nz + 2) * (KC + 1) * 8 + 15) / 16 * 16 + (size_t)KC * 32 + (size_t)nwaves * nz * 8;
+    // slice totals: one row of nz per builder (a wave, or half a wave for depths of 32 or less)
+    return ((size_t)(nz + 2) * (KC + 1) * 8 + 15) / 16 * 16 + (size_t)KC * 32 +
+           (size_t)(nz <= 32 ? 2 * nwaves : nwaves) * nz * 8;
 }
 
 template <int KC, int NPT>
@@ -280,8 +282,13 @@ __device__ __forceinline__ void forward_runs_body(const float *__restrict__ vol_
     // voxel loads through a raw buffer: 32-bit byte offsets, one add each
     const __amdgpu_buffer_rsrc_t vrs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(vol_t), 0, nx * ny * nz * 4, 0x00020000);
-    const int sc = ((KC + nw - 1) / nw + 7) & ~7;  // slices of whole groups of 8 samples
-    const int ka = min(wave * sc, KC), kb = min(ka + sc, KC);
+    // the build maps lanes to z cells; at depths of 32 or less each wave's halves take different
+    // slices of samples (builder vw, lane vl), so that no lane idles
+    const int half = nz <= 32 ? 1 : 0;
+    const int vw = half ? 2 * wave + (lane >> 5) : wave, vl = half ? (lane & 31) : lane;
+    const int nvw = half ? 2 * nw : nw, lstep = half ? 32 : 64;
+    const int sc = ((KC + nvw - 1) / nvw + 7) & ~7;  // slices of whole groups of 8 samples
+    const int ka = min(vw * sc, KC), kb = min(ka + sc, KC);
 
     for (int k0 = cp.klo; k0 <= cp.khi; k0 += KC) {
         __syncthreads();  // the previous chunk's rays are done with the tables
@@ -304,7 +311,7 @@ __device__ __forceinline__ void forward_runs_body(const float *__restrict__ vol_
         // prefix sums of this wave's slice of samples, lane = z cell; groups of RB samples read
         // their weights first and keep all their voxel loads in flight together
         constexpr int RB = 8;
-        for (int c = lane; c < nz; c += 64) {
+        for (int c = vl; c < nz; c += lstep) {
             float A = 0.0f, K = 0.0f;
             float2 *row = tab + (c + 1) * S + 1;  // entry k + 1 holds the sums over samples < k + 1
             const int c4 = c * 4;
@@ -334,13 +341,13 @@ __device__ __forceinline__ void forward_runs_body(const float *__restrict__ vol_
                     row[kk + u] = make_float2(A, K);
                 }
             }
-            tot[wave * nz + c] = make_float2(A, K);
+            tot[vw * nz + c] = make_float2(A, K);
         }
         __syncthreads();
-        if (wave > 0) {
-            for (int c = lane; c < nz; c += 64) {
+        if (vw > 0) {
+            for (int c = vl; c < nz; c += lstep) {
                 float2 off = tot[c];
-                for (int w2 = 1; w2 < wave; w2++) {
+                for (int w2 = 1; w2 < vw; w2++) {
                     const float2 t = tot[w2 * nz + c];
                     off.x += t.x;
                     off.y += t.y;

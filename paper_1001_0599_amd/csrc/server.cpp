@@ -114,6 +114,7 @@ struct Request {
     // Step 2 of the current outer iteration: a gated loop ran (Step 3 applies its pending step);
     // the sequence numbers of the steps enqueued for it
     bool pending = false;
+    bool fresh = false;  // this round's loop is its first device-side Step 2
     std::vector<int> seqs;
 };
 
@@ -478,23 +479,12 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
         if (r->p.rof_max_iter > 0) rof.push_back(r);
     }
     if (!rof.empty()) {
-        // new loops; the records and replay position (unused here) are reset once per request
-        std::vector<RofGate *> gates;
-        std::vector<RofLog *> sts;
-        std::vector<Request *> fresh_state, kept_state;
-        for (Request *r : rof) (r->dev_init ? kept_state : fresh_state).push_back(r);
-        for (int pass = 0; pass < 2; pass++) {
-            const auto &grp = pass == 0 ? fresh_state : kept_state;
-            if (grp.empty()) continue;
-            gates.clear();
-            sts.clear();
-            for (Request *r : grp) {
-                gates.push_back(r->b.gate);
-                sts.push_back(r->b.sst);
-                r->dev_init = true;
-            }
-            if ((st = cbct_launch_rof_gate_init_batch(gates.data(), sts.data(), (int)grp.size(), pass == 0, st_)))
-                return st;
+        // new loops: their first step's decision starts each loop's state, and a request's records
+        // and replay position (unused here) the first time it runs a device-side Step 2
+        std::vector<char> fresh(rof.size());
+        for (size_t q = 0; q < rof.size(); q++) {
+            fresh[q] = !rof[q]->dev_init;
+            rof[q]->dev_init = true;
         }
         long max_steps = 0;
         for (Request *r : rof) {
@@ -503,6 +493,7 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
             max_steps = std::max(max_steps, (long)r->p.rof_max_iter * (2 + r->p.rof_max_backtrack / CBCT_TRIALS));
         }
         std::vector<Request *> active = rof;
+        for (size_t q = 0; q < rof.size(); q++) rof[q]->fresh = fresh[q] != 0;
         std::vector<const Level *> lv;
         std::vector<RofStepArgs> args;
         long issued = 0, known = 0;
@@ -535,6 +526,7 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
                     a.mirror = s->mirror_dev ? &s->mirror_dev[r->slot].pad : nullptr;
                     a.seq = (s->seq.fetch_add(1) + 1) & CBCT_GATE_SEQ_MASK;
                     a.first = issued == 0 ? 1 : 0;
+                    a.init_state = (issued == 0 && r->fresh) ? 1 : 0;
                     r->seqs.push_back(a.seq);
                     lv.push_back(&L);
                     args.push_back(a);

@@ -358,7 +358,6 @@ cbct_status rof_loop_gated(const Level &L, const cbct_solve_params *pr, double t
                            int level, int outer, bool first, int replay_pos, bool records, bool apply_pending) {
     constexpr int AHEAD = 2;
     cbct_status st;
-    if ((st = cbct_launch_rof_gate_init(b.gate, b.sst, replay_pos, first, s))) return st;
     const MappedSlot ms = mapped_ctl();
     RofStepArgs a{};
     a.eps = pr->tv_eps;
@@ -393,6 +392,8 @@ cbct_status rof_loop_gated(const Level &L, const cbct_solve_params *pr, double t
         while ((long)seqs.size() < max_steps && (long)seqs.size() < known + AHEAD) {
             a.seq = next_seq();
             a.first = seqs.empty() ? 1 : 0;
+            a.init_state = (a.first && first) ? 1 : 0;
+            a.replay_pos = replay_pos;
             seqs.push_back(a.seq);
             if ((st = cbct_launch_rof_step_gated(L, a, s))) return st;
         }

@@ -98,6 +98,112 @@ __device__ __forceinline__ RowIter row_iter(const TVShape &k, const Blk2 &B) {
     return it;
 }
 
+// ---- per-voxel passes (small volumes: too few tiled work items to fill the GPU) -------------
+// Each thread computes its voxel's own and its three lower neighbours' q from u directly.
+// d = lambda * N dR/du + (u - g)/t (g may be NULL: then d = N dR/du and lambda is ignored).
+// partials[block] = {sum phi, sum (u-g)^2, sum d^2}.
+__device__ __forceinline__ void tv_grad_rows(const float *__restrict__ u, const float *__restrict__ g,
+                                             float *__restrict__ d, const TVShape &k, float lambda, float inv_t,
+                                             double *__restrict__ partials, const Blk2 &B) {
+    __shared__ double sh[4];
+    const long nxy = (long)k.nx * k.ny;
+    double s_phi = 0.0, s_fid = 0.0, s_d2 = 0.0;
+    const RowIter ri = row_iter(k, B);
+    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
+        const int c = row / k.ny, b = row - c * k.ny;
+        const long rbase = (long)c * nxy + (long)b * k.nx;
+        for (int a = ri.a0; a < k.nx; a += ri.astep) {
+            const long p = rbase + a;
+            float dx, dy, dz;
+            diffs(u, p, a, b, c, k, dx, dy, dz);
+            const float ph = phi_of(dx, dy, dz, k.eps2);
+            const float ip = __builtin_amdgcn_rcpf(ph);  // 1 ulp reciprocals instead of divisions
+            // the z difference of the last plane is identically 0 (reflective ghost): q_z = 0 there
+            float div = -(dx * ip * k.ihx + dy * ip * k.ihy + dz * ip * k.ihz);
+            if (a >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - 1, a - 1, b, c, k, ex, ey, ez);
+                div += ex * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihx;
+            }
+            if (b >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - k.nx, a, b - 1, c, k, ex, ey, ez);
+                div += ey * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihy;
+            }
+            if (c >= 1) {
+                float ex, ey, ez;
+                diffs(u, p - nxy, a, b, c - 1, k, ex, ey, ez);
+                div += ez * __builtin_amdgcn_rcpf(phi_of(ex, ey, ez, k.eps2)) * k.ihz;
+            }
+            float dv;
+            if (g) {
+                const float r = u[p] - g[p];
+                dv = fmaf(lambda, div, r * inv_t);
+                s_fid += (double)r * (double)r;
+            } else {
+                dv = div;
+            }
+            d[p] = dv;
+            s_phi += (double)ph;
+            s_d2 += (double)dv * (double)dv;
+        }
+    }
+    const int blk = B.by * B.gx + B.bx;
+    double v;
+    v = block_sum(s_phi, sh);
+    if (threadIdx.x == 0) partials[blk * 3 + 0] = v;
+    v = block_sum(s_fid, sh);
+    if (threadIdx.x == 0) partials[blk * 3 + 1] = v;
+    v = block_sum(s_d2, sh);
+    if (threadIdx.x == 0) partials[blk * 3 + 2] = v;
+}
+
+// Trial energies at s_m = s0 * alpha^m, m < M.  partials[block][2m + {0,1}] = {sum phi, sum fid}.
+template <int M>
+__device__ __forceinline__ void tv_trial_rows(const float *__restrict__ u, const float *__restrict__ d,
+                                              const float *__restrict__ g, const TVShape &k, double t, double alpha,
+                                              int m0, double *__restrict__ partials, const Blk2 &B) {
+    __shared__ double sh[4];
+    const long nxy = (long)k.nx * k.ny;
+    // s_m = t alpha^(m0 + m), formed exactly as the decision kernel forms it
+    float s[M];
+    double sd = t;
+    for (int m = 0; m < m0; m++) sd *= alpha;
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        s[m] = (float)sd;
+        sd *= alpha;
+    }
+    double s_phi[M], s_fid[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) s_phi[m] = s_fid[m] = 0.0;
+    const RowIter ri = row_iter(k, B);
+    for (int row = ri.row0; row < ri.nrow; row += ri.rstep) {
+        const int c = row / k.ny, b = row - c * k.ny;
+        const long rbase = (long)c * nxy + (long)b * k.nx;
+        for (int a = ri.a0; a < k.nx; a += ri.astep) {
+            const long p = rbase + a;
+            const float gp = g[p];
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                float w0, dx, dy, dz;
+                diffs_step(u, d, s[m], p, a, b, c, k, w0, dx, dy, dz);
+                const float r = w0 - gp;
+                s_phi[m] += (double)phi_of(dx, dy, dz, k.eps2);
+                s_fid[m] += (double)r * (double)r;
+            }
+        }
+    }
+    const int blk = B.by * B.gx + B.bx;
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        double v = block_sum(s_phi[m], sh);
+        if (threadIdx.x == 0) partials[blk * 2 * M + 2 * m] = v;
+        v = block_sum(s_fid[m], sh);
+        if (threadIdx.x == 0) partials[blk * 2 * M + 2 * m + 1] = v;
+    }
+}
+
 // ---- tiled passes: d and the trial energies with the stencil values computed once per voxel ----
 // A wave owns a work item: 64 consecutive x (one per lane) x TV_TY rows x zc planes.  It walks
 // the item's planes in order and, in every plane, its rows in order, so what a voxel's divergence
@@ -345,10 +451,25 @@ __device__ __forceinline__ void tv_grad_body(const float *__restrict__ u, const 
     if (threadIdx.x == 0) partials[blk * 3 + 2] = v;
 }
 
+// The layout of a volume's gradient and trial passes: tiled items, or per-voxel rows on a
+// (gx, gy) grid of (64-voxel row segment, 4 rows) tiles; nb work-groups in a 1-D launch either way
+// (and nb rows of partial sums).
+struct TvGrid {
+    TvItems T;
+    int tiled, gx, gy, nb;
+};
+
+__device__ __forceinline__ void tv_grad_any(const float *__restrict__ u, const float *__restrict__ g,
+                                            float *__restrict__ d, const TVShape &k, float lambda, float inv_t,
+                                            const TvGrid &G, double *__restrict__ partials, int blk) {
+    if (G.tiled) tv_grad_body(u, g, d, k, lambda, inv_t, G.T, partials, blk, G.nb);
+    else tv_grad_rows(u, g, d, k, lambda, inv_t, partials, Blk2{blk % G.gx, blk / G.gx, G.gx, G.gy});
+}
+
 __global__ void __launch_bounds__(256) k_tv_grad(const float *__restrict__ u, const float *__restrict__ g,
                                                  float *__restrict__ d, TVShape k, float lambda, float inv_t,
-                                                 TvItems T, double *__restrict__ partials) {
-    tv_grad_body(u, g, d, k, lambda, inv_t, T, partials, blockIdx.x, gridDim.x);
+                                                 TvGrid G, double *__restrict__ partials) {
+    tv_grad_any(u, g, d, k, lambda, inv_t, G, partials, blockIdx.x);
 }
 
 // sum phi only (energy of a volume)
@@ -403,10 +524,18 @@ __device__ __forceinline__ void tv_trial_body(const float *__restrict__ u, const
 }
 
 template <int M>
+__device__ __forceinline__ void tv_trial_any(const float *__restrict__ u, const float *__restrict__ d,
+                                             const float *__restrict__ g, const TVShape &k, double t, double alpha,
+                                             int m0, const TvGrid &G, double *__restrict__ partials, int blk) {
+    if (G.tiled) tv_trial_body<M>(u, d, g, k, t, alpha, m0, G.T, partials, blk, G.nb);
+    else tv_trial_rows<M>(u, d, g, k, t, alpha, m0, partials, Blk2{blk % G.gx, blk / G.gx, G.gx, G.gy});
+}
+
+template <int M>
 __global__ void __launch_bounds__(256) k_tv_trial(const float *__restrict__ u, const float *__restrict__ d,
                                                   const float *__restrict__ g, TVShape k, double t, double alpha,
-                                                  int m0, TvItems T, double *__restrict__ partials) {
-    tv_trial_body<M>(u, d, g, k, t, alpha, m0, T, partials, blockIdx.x, gridDim.x);
+                                                  int m0, TvGrid G, double *__restrict__ partials) {
+    tv_trial_any<M>(u, d, g, k, t, alpha, m0, G, partials, blockIdx.x);
 }
 
 // sum of `nb` rows of `width` partials: out[j] = sum_b part[b * width + j], in a fixed order
@@ -691,20 +820,6 @@ __global__ void __launch_bounds__(SMALL_THREADS)
 // between ROF iterations or backtracking windows.  The passes are the multi-kernel path's, and
 // the decision kernel forms the sums in k_sum_rows's order and decides with the same body, so the
 // results are bitwise those of a host-driven loop over the same kernels.
-__global__ void k_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, int init_state) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    RofGate g{};
-    g.run = 1;
-    g.grad = 1;
-    *gate = g;
-    if (init_state) {
-        st->n_rec = 0;
-        st->replay_pos = replay_pos;
-        st->status = 0;
-        st->pad = 0;
-    }
-}
-
 __global__ void k_axpy_gated(float *__restrict__ u, const float *__restrict__ d, const RofControl *__restrict__ ctl,
                              const RofGate *__restrict__ gate, long n, int pending_only) {
     const bool on = pending_only ? gate->pending != 0 : (gate->run != 0 && gate->apply != 0);
@@ -714,27 +829,27 @@ __global__ void k_axpy_gated(float *__restrict__ u, const float *__restrict__ d,
 
 __global__ void __launch_bounds__(256) k_tv_grad_gated(const float *__restrict__ u, const float *__restrict__ g,
                                                        float *__restrict__ d, TVShape k, float lambda, float inv_t,
-                                                       TvItems T, double *__restrict__ partials,
+                                                       TvGrid G, double *__restrict__ partials,
                                                        const RofGate *__restrict__ gate) {
     if (!gate->run || !gate->grad) return;
-    tv_grad_body(u, g, d, k, lambda, inv_t, T, partials, blockIdx.x, gridDim.x);
+    tv_grad_any(u, g, d, k, lambda, inv_t, G, partials, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_tv_trial_gated(const float *__restrict__ u, const float *__restrict__ d,
                                                         const float *__restrict__ g, TVShape k, double t,
-                                                        double alpha, TvItems T, double *__restrict__ partials,
+                                                        double alpha, TvGrid G, double *__restrict__ partials,
                                                         const RofGate *__restrict__ gate) {
     if (!gate->run) return;
     const int m0 = gate->m0;
     // the first window tries the full step only, later ones CBCT_TRIALS step sizes
-    if (m0 == 0) tv_trial_body<1>(u, d, g, k, t, alpha, 0, T, partials, blockIdx.x, gridDim.x);
-    else tv_trial_body<CBCT_TRIALS>(u, d, g, k, t, alpha, m0, T, partials, blockIdx.x, gridDim.x);
+    if (m0 == 0) tv_trial_any<1>(u, d, g, k, t, alpha, 0, G, partials, blockIdx.x);
+    else tv_trial_any<CBCT_TRIALS>(u, d, g, k, t, alpha, m0, G, partials, blockIdx.x);
 }
 
 struct GateDecide {
     const double *pg, *pt;  // gradient and trial partials
     double *sums;
-    int nb;
+    int nb;  // rows of gradient and of trial partials
     double inv_n, lambda, t, c_armijo, alpha, tol;
     int max_iter, max_bt;
     RofControl *ctl;
@@ -746,6 +861,9 @@ struct GateDecide {
     int rec_cap, level, outer;
     int *mirror;
     int seq;
+    int first;       // the loop's first step: the state starts fresh here (no reset launch)
+    int init_state;  // with first: the level's first loop (records and replay position start too)
+    int replay_pos;  // with init_state: the replay position at the level's start
 };
 
 // the decision of a gated step (one work-group of 256 threads): the fixed-order sums of the step's
@@ -753,9 +871,9 @@ struct GateDecide {
 __device__ __forceinline__ void gate_decide_body(const GateDecide &A) {
     __shared__ int run_s, grad_s, m0_s;
     if (threadIdx.x == 0) {
-        run_s = A.gate->run;
-        grad_s = A.gate->grad;
-        m0_s = A.gate->m0;
+        run_s = A.first ? 1 : A.gate->run;
+        grad_s = A.first ? 1 : A.gate->grad;
+        m0_s = A.first ? 0 : A.gate->m0;
     }
     __syncthreads();
     if (!run_s) return;
@@ -765,8 +883,16 @@ __device__ __forceinline__ void gate_decide_body(const GateDecide &A) {
     sum_rows_body(A.pt, A.nb, 2 * M, A.sums + 3);
     __syncthreads();
     if (threadIdx.x != 0) return;
-    RofGate G = *A.gate;
-    RofLog S = *A.st;
+    RofGate G{};
+    if (A.first) {
+        G.run = 1;
+        G.grad = 1;
+    } else {
+        G = *A.gate;
+    }
+    RofLog S{};
+    if (A.first && A.init_state) S.replay_pos = A.replay_pos;
+    else S = *A.st;
     // the replayed decision of this ROF iteration, if any (applies to all of its windows)
     int forced = -2, fend = -1;
     if (A.replay && S.replay_pos < A.replay_len) {
@@ -848,12 +974,13 @@ struct BStepItem {
     TVShape k;
     float lambda, inv_t;
     double t, alpha;
-    TvItems T;
+    TvGrid G;     // layout of its gradient and trial passes (nb: their work-groups)
     long n;
-    int nb, nba;  // TV work-groups, update work-groups
+    int nba;      // its update work-groups
 };
 struct BStep {
     int n;
+    int first;               // the loops' first step: the passes run without reading any state
     int wg0[CBCT_MAXB + 1];  // exclusive prefix of the TV passes' work-groups
     int wa0[CBCT_MAXB + 1];  // the same for the update pass
     BStepItem it[CBCT_MAXB];
@@ -876,48 +1003,28 @@ __global__ void k_axpy_gated_b(BStep B) {
 __global__ void __launch_bounds__(256) k_tv_grad_gated_b(BStep B) {
     const int r = batch_of(B.wg0, B.n, blockIdx.x);
     const BStepItem &it = B.it[r];
-    if (!it.gate->run || !it.gate->grad) return;
-    tv_grad_body(it.u, it.g, it.d, it.k, it.lambda, it.inv_t, it.T, it.pg, blockIdx.x - B.wg0[r], it.nb);
+    if (!B.first && (!it.gate->run || !it.gate->grad)) return;
+    tv_grad_any(it.u, it.g, it.d, it.k, it.lambda, it.inv_t, it.G, it.pg, blockIdx.x - B.wg0[r]);
 }
 
 __global__ void __launch_bounds__(256) k_tv_trial_gated_b(BStep B) {
     const int r = batch_of(B.wg0, B.n, blockIdx.x);
     const BStepItem &it = B.it[r];
-    if (!it.gate->run) return;
-    const int m0 = it.gate->m0, local = blockIdx.x - B.wg0[r];
-    if (m0 == 0) tv_trial_body<1>(it.u, it.d, it.g, it.k, it.t, it.alpha, 0, it.T, it.pt, local, it.nb);
-    else tv_trial_body<CBCT_TRIALS>(it.u, it.d, it.g, it.k, it.t, it.alpha, m0, it.T, it.pt, local, it.nb);
+    if (!B.first && !it.gate->run) return;
+    const int m0 = B.first ? 0 : it.gate->m0, local = blockIdx.x - B.wg0[r];
+    if (m0 == 0) tv_trial_any<1>(it.u, it.d, it.g, it.k, it.t, it.alpha, 0, it.G, it.pt, local);
+    else tv_trial_any<CBCT_TRIALS>(it.u, it.d, it.g, it.k, it.t, it.alpha, m0, it.G, it.pt, local);
 }
 
 struct BDecide {
     int n;
     GateDecide it[CBCT_MAXB];
 };
+// kernel arguments are at most 4 KB
+static_assert(sizeof(BStep) <= 4096 && sizeof(BDecide) <= 4096, "batched step arguments");
 
 // one work-group per request
 __global__ void __launch_bounds__(256) k_rof_decide_gated_b(BDecide B) { gate_decide_body(B.it[blockIdx.x]); }
-
-struct BInit {
-    int n, init_state;
-    RofGate *gate[CBCT_MAXB];
-    RofLog *st[CBCT_MAXB];
-};
-
-__global__ void k_rof_gate_init_b(BInit B) {
-    const int r = threadIdx.x;
-    if (blockIdx.x != 0 || r >= B.n) return;
-    RofGate g{};
-    g.run = 1;
-    g.grad = 1;
-    *B.gate[r] = g;
-    if (B.init_state) {
-        RofLog *st = B.st[r];
-        st->n_rec = 0;
-        st->replay_pos = 0;
-        st->status = 0;
-        st->pad = 0;
-    }
-}
 
 }  // namespace
 
@@ -942,9 +1049,27 @@ static int tv_blocks(const TvItems &T) {
     return (int)std::min<long>((T.n() + 3) / 4, CBCT_RED_BLOCKS);
 }
 
+// the tiled walk where the volume gives at least 1024 items (4096 at 512x512x64, 1024 at 128^3),
+// the per-voxel passes below that (a 32^3 volume makes 32 items: eight work-groups walking their
+// items serially, against 256 work-groups of independent voxels)
+static TvGrid tv_layout(const Level &L) {
+    TvGrid G{};
+    G.T = tv_items(L.nx, L.ny, L.nz);
+    G.tiled = G.T.n() >= 1024;
+    if (G.tiled) {
+        G.nb = tv_blocks(G.T);
+    } else {
+        const dim3 g = tv_grid(L);
+        G.gx = (int)g.x;
+        G.gy = (int)g.y;
+        G.nb = G.gx * G.gy;
+    }
+    return G;
+}
+
 int cbct_reduce_blocks(const Level &L) {
     const dim3 g = tv_grid(L);
-    return std::max((int)(g.x * g.y), tv_blocks(tv_items(L.nx, L.ny, L.nz)));
+    return std::max((int)(g.x * g.y), tv_layout(L).nb);
 }
 
 #define LAUNCH_CHECK(what)                                  \
@@ -955,10 +1080,10 @@ int cbct_reduce_blocks(const Level &L) {
 
 cbct_status cbct_launch_tv_grad(const Level &L, double eps, const float *u, const float *g, float *d, double lambda,
                                 double t, double *partials, double *sums, hipStream_t s) {
-    const TvItems T = tv_items(L.nx, L.ny, L.nz);
-    const int nb = tv_blocks(T);
+    const TvGrid G = tv_layout(L);
+    const int nb = G.nb;
     hipLaunchKernelGGL(k_tv_grad, dim3(nb), dim3(256), 0, s, u, g, d, tv_shape(L, eps), (float)lambda,
-                       (float)(1.0 / t), T, partials);
+                       (float)(1.0 / t), G, partials);
     LAUNCH_CHECK("k_tv_grad");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 3, sums);
     LAUNCH_CHECK("k_sum_rows");
@@ -978,14 +1103,14 @@ cbct_status cbct_launch_tv_energy(const Level &L, double eps, const float *u, do
 
 cbct_status cbct_launch_tv_trial(const Level &L, double eps, const float *u, const float *d, const float *g,
                                  double t, double alpha, int m0, int M, double *partials, double *sums, hipStream_t s) {
-    const TvItems T = tv_items(L.nx, L.ny, L.nz);
-    const int nb = tv_blocks(T);
+    const TvGrid G = tv_layout(L);
+    const int nb = G.nb;
     if (M == 1)
-        hipLaunchKernelGGL((k_tv_trial<1>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha, m0, T,
+        hipLaunchKernelGGL((k_tv_trial<1>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t, alpha, m0, G,
                            partials);
     else
         hipLaunchKernelGGL((k_tv_trial<CBCT_TRIALS>), dim3(nb), dim3(256), 0, s, u, d, g, tv_shape(L, eps), t,
-                           alpha, m0, T, partials);
+                           alpha, m0, G, partials);
     LAUNCH_CHECK("k_tv_trial");
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, partials, nb, 2 * (M == 1 ? 1 : CBCT_TRIALS), sums);
     LAUNCH_CHECK("k_sum_rows");
@@ -1029,13 +1154,6 @@ cbct_status cbct_launch_rof_small(const Level &L, double eps, float *u, const fl
     return CBCT_OK;
 }
 
-cbct_status cbct_launch_rof_gate_init(RofGate *gate, RofLog *st, int replay_pos, bool init_state,
-                                      hipStream_t s) {
-    hipLaunchKernelGGL(k_rof_gate_init, dim3(1), dim3(64), 0, s, gate, st, replay_pos, init_state ? 1 : 0);
-    LAUNCH_CHECK("k_rof_gate_init");
-    return CBCT_OK;
-}
-
 static GateDecide gate_decide_args(const Level &L, const RofStepArgs &a, int nb) {
     GateDecide D;
     D.pg = a.part;
@@ -1061,26 +1179,38 @@ static GateDecide gate_decide_args(const Level &L, const RofStepArgs &a, int nb)
     D.outer = a.outer;
     D.mirror = a.mirror;
     D.seq = a.seq & CBCT_GATE_SEQ_MASK;
+    D.first = a.first;
+    D.init_state = a.init_state;
+    D.replay_pos = a.replay_pos;
     return D;
 }
 
 cbct_status cbct_launch_rof_step_gated(const Level &L, const RofStepArgs &a, hipStream_t s) {
     const long n = L.nvox();
     const int nba = (int)std::min<long>((n + 255) / 256, 4096);
-    const TvItems T = tv_items(L.nx, L.ny, L.nz);
-    const int nb = tv_blocks(T);
+    const TvGrid G = tv_layout(L);
     const TVShape k = tv_shape(L, a.eps);
     double *pt = a.part + 3 * (size_t)CBCT_RED_BLOCKS;
-    if (!a.first) {
+    if (a.first) {
+        // the loop's first step always runs a gradient and the full-step trial: the passes need
+        // no state, and the decision starts the state (no reset launch)
+        hipLaunchKernelGGL(k_tv_grad, dim3(G.nb), dim3(256), 0, s, a.u, a.g, a.d, k, (float)a.lambda,
+                           (float)(1.0 / a.t), G, a.part);
+        LAUNCH_CHECK("k_tv_grad");
+        hipLaunchKernelGGL((k_tv_trial<1>), dim3(G.nb), dim3(256), 0, s, a.u, a.d, a.g, k, a.t, a.alpha, 0, G,
+                           pt);
+        LAUNCH_CHECK("k_tv_trial");
+    } else {
         hipLaunchKernelGGL(k_axpy_gated, dim3(nba), dim3(256), 0, s, a.u, a.d, a.ctl, a.gate, n, 0);
         LAUNCH_CHECK("k_axpy_gated");
+        hipLaunchKernelGGL(k_tv_grad_gated, dim3(G.nb), dim3(256), 0, s, a.u, a.g, a.d, k, (float)a.lambda,
+                           (float)(1.0 / a.t), G, a.part, a.gate);
+        LAUNCH_CHECK("k_tv_grad_gated");
+        hipLaunchKernelGGL(k_tv_trial_gated, dim3(G.nb), dim3(256), 0, s, a.u, a.d, a.g, k, a.t, a.alpha, G, pt,
+                           a.gate);
+        LAUNCH_CHECK("k_tv_trial_gated");
     }
-    hipLaunchKernelGGL(k_tv_grad_gated, dim3(nb), dim3(256), 0, s, a.u, a.g, a.d, k, (float)a.lambda,
-                       (float)(1.0 / a.t), T, a.part, a.gate);
-    LAUNCH_CHECK("k_tv_grad_gated");
-    hipLaunchKernelGGL(k_tv_trial_gated, dim3(nb), dim3(256), 0, s, a.u, a.d, a.g, k, a.t, a.alpha, T, pt, a.gate);
-    LAUNCH_CHECK("k_tv_trial_gated");
-    const GateDecide D = gate_decide_args(L, a, nb);
+    const GateDecide D = gate_decide_args(L, a, G.nb);
     hipLaunchKernelGGL(k_rof_decide_gated, dim3(1), dim3(256), 0, s, D);
     LAUNCH_CHECK("k_rof_decide_gated");
     return CBCT_OK;
@@ -1095,29 +1225,13 @@ cbct_status cbct_launch_axpy_pending(float *u, const float *d, const RofControl 
 }
 
 // ---- batched launchers ---------------------------------------------------------------------
-cbct_status cbct_launch_rof_gate_init_batch(RofGate *const *gate, RofLog *const *st, int n, bool init_state,
-                                            hipStream_t s) {
-    for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
-        const int m = std::min(CBCT_MAXB, n - q0);
-        BInit B{};
-        B.n = m;
-        B.init_state = init_state ? 1 : 0;
-        for (int q = 0; q < m; q++) {
-            B.gate[q] = gate[q0 + q];
-            B.st[q] = st[q0 + q];
-        }
-        hipLaunchKernelGGL(k_rof_gate_init_b, dim3(1), dim3(64), 0, s, B);
-        LAUNCH_CHECK("k_rof_gate_init_b");
-    }
-    return CBCT_OK;
-}
-
 cbct_status cbct_launch_rof_step_gated_batch(const Level *const *L, const RofStepArgs *a, int n, hipStream_t s) {
     for (int q0 = 0; q0 < n; q0 += CBCT_MAXB) {
         const int m = std::min(CBCT_MAXB, n - q0);
         BStep B{};
         BDecide D{};
         B.n = D.n = m;
+        B.first = a[q0].first;  // the steps of one batch are all first steps or none is
         int w = 0, wa = 0;
         for (int q = 0; q < m; q++) {
             const Level &Lq = *L[q0 + q];
@@ -1135,19 +1249,18 @@ cbct_status cbct_launch_rof_step_gated_batch(const Level *const *L, const RofSte
             it.inv_t = (float)(1.0 / aq.t);
             it.t = aq.t;
             it.alpha = aq.alpha;
-            it.T = tv_items(Lq.nx, Lq.ny, Lq.nz);
+            it.G = tv_layout(Lq);
             it.n = Lq.nvox();
-            it.nb = tv_blocks(it.T);
             it.nba = (int)std::min<long>((it.n + 255) / 256, 4096);
             B.wg0[q] = w;
             B.wa0[q] = wa;
-            w += it.nb;
+            w += it.G.nb;
             wa += it.nba;
-            D.it[q] = gate_decide_args(Lq, aq, it.nb);
+            D.it[q] = gate_decide_args(Lq, aq, it.G.nb);
         }
         B.wg0[m] = w;
         B.wa0[m] = wa;
-        if (!a[q0].first) {  // the steps of one batch are all first steps or none is
+        if (!B.first) {
             hipLaunchKernelGGL(k_axpy_gated_b, dim3(wa), dim3(256), 0, s, B);
             LAUNCH_CHECK("k_axpy_gated_b");
         }
