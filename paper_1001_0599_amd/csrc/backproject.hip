@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(256)
 // tiles of 32 cells beat tiles of 64 (whole profile rows, 2 work-groups per CU: 2.16 against 1.99
 // ms per P^T in one group).
 constexpr int GS_ROWS32 = 320;
+typedef float v4f __attribute__((ext_vector_type(4)));  // a native vector for the non-temporal builtin
 constexpr int GS_CC = 64;  // detector columns per column chunk (one wave lists them)
 
 struct GsCol {
@@ -308,7 +309,10 @@ __global__ void __launch_bounds__(256)
                     for (int j = 0; j < PER; j++) {
                         // items past the batch load its last row again (no branch between the loads)
                         const int it = min(tid + 256 * j, items - 1);
-                        v[j] = *reinterpret_cast<const float4 *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1)));
+                        // a non-temporal load: these profile lines are read once, from HBM
+                        const v4f t = __builtin_nontemporal_load(
+                            reinterpret_cast<const v4f *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1))));
+                        v[j] = make_float4(t.x, t.y, t.z, t.w);
                     }
                     // all loads in flight before the first store: an empty asm statement consumes
                     // every loaded word here, so the compiler cannot sink (or split) each load

@@ -247,9 +247,9 @@ struct TraceSink {
     }
 };
 
-// Reads back the device-side Step 2 of a small level: its state (replay records consumed, a
+// Reads back a level's device-side Step 2 log: its state (replay records consumed, a
 // non-finite energy) and, for the caller's statistics, its per-iteration records in order.
-cbct_status flush_small(const Bufs &b, hipStream_t s, TraceSink &sink, int *replay_pos) {
+cbct_status flush_step2_log(const Bufs &b, hipStream_t s, TraceSink &sink, int *replay_pos) {
     RofLog st;
     CBCT_HIP(hipMemcpyAsync(&st, b.sst, sizeof(st), hipMemcpyDeviceToHost, s));
     CBCT_HIP(hipStreamSynchronize(s));
@@ -271,15 +271,13 @@ cbct_status flush_small(const Bufs &b, hipStream_t s, TraceSink &sink, int *repl
     return CBCT_OK;
 }
 
-// Step 2: u = ROF(g) from u = g (u_ready: Step 1 has written u already).  `replay_pos` walks
-// params.replay.  With `pending`, an accepted step that ends the loop is not applied to u; the
-// caller's Step 3 applies it (*pending = true, the step in b.ctl).
+// Step 2 driven from the host (Step 2 alone with a replay, or with more ROF iterations than its
+// record buffer holds): u = ROF(g) from u = g, one read of the device's decision per backtracking
+// window.  `replay_pos` walks params.replay.
 cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, const Bufs &b, hipStream_t s,
-                     TraceSink &sink, int level, int outer, int *replay_pos, bool u_ready = false,
-                     bool *pending = nullptr) {
-    if (pending) *pending = false;
+                     TraceSink &sink, int level, int outer, int *replay_pos) {
     cbct_status st;
-    if (!u_ready) CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < pr->rof_max_iter; it++) {
         int forced = -2;      // free running
         int forced_end = -1;  // replayed: 1 when this record ends Step 2
@@ -337,10 +335,6 @@ cbct_status rof_loop(const Level &L, const cbct_solve_params *pr, double t, cons
         if (c.accepted != 1) break;  // Eq. 5 held for no step: keep u
         const bool own_stop = c.e0 == 0.0 || c.G == 0.0 || std::fabs(c.e_trial - c.e0) / c.e0 < pr->rof_tol;
         const bool stop = (forced_end >= 0 ? forced_end == 1 : own_stop) || it + 1 == pr->rof_max_iter;
-        if (stop && pending) {
-            *pending = true;
-            break;
-        }
         if ((st = cbct_launch_axpy_step(b.u, b.d, b.ctl, L.nvox(), s))) return st;
         if (stop) break;
     }
@@ -584,7 +578,7 @@ extern "C" cbct_status cbct_reconstruct(cbct_plan *p, const cbct_solve_params *p
                                                 pending ? b.ctl : nullptr)))
                 return st;
         }
-        if (dev_ran && (st = flush_small(b, s, sink, &replay_pos))) return st;
+        if (dev_ran && (st = flush_step2_log(b, s, sink, &replay_pos))) return st;
     }
     CBCT_HIP(hipMemcpyAsync(d_out, b.f, sizeof(float) * L0.nvox(), hipMemcpyDeviceToDevice, s));
     if (stats) {
@@ -643,12 +637,12 @@ extern "C" cbct_status cbct_tv_prox(cbct_plan *p, int level, const cbct_solve_pa
                                         pr->rof_tol, pr->rof_max_iter, pr->rof_max_backtrack, nullptr, 0, 0, b.sst,
                                         b.rec, b.rec_cap, level, 0, true, s)))
             return st;
-        if ((st = flush_small(b, s, sink, &pos))) return st;
+        if ((st = flush_step2_log(b, s, sink, &pos))) return st;
     } else if (!pr->replay && pr->rof_max_iter > 0 && (!stats || pr->rof_max_iter <= b.rec_cap)) {
         // gated launch chains, records read back once
         CBCT_HIP(hipMemcpyAsync(b.u, b.g, sizeof(float) * L.nvox(), hipMemcpyDeviceToDevice, s));
         if ((st = rof_loop_gated(L, pr, pr->step, b, s, level, 0, true, 0, stats != nullptr, true))) return st;
-        if ((st = flush_small(b, s, sink, &pos))) return st;
+        if ((st = flush_step2_log(b, s, sink, &pos))) return st;
     } else if ((st = rof_loop(L, pr, pr->step, b, s, sink, level, 0, &pos))) {
         return st;
     }

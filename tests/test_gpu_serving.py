@@ -77,6 +77,28 @@ def test_mixed_operator_choices_equal_solo_results():
     srv.close()
 
 
+def test_multilevel_requests_equal_solo_results():
+    """Two-level requests through the batch engines: the coarse level of a 32^3 request (16^3)
+    runs Step 2 in one work-group and its fine level as gated steps, larger ones gated on both
+    levels; every result equals its solo solve bitwise."""
+    from paper_1001_0599_amd.ops import Plan
+    from paper_1001_0599_amd.serving import Server
+    announce("serving: 4 two-level requests, 4 slots")
+    reqs = _requests()[:4]
+    iters = (3, 5)
+    solo = [Plan(g, levels=2).reconstruct(y, lam=0.05, iters=list(iters)) for g, y in reqs]
+    torch.cuda.synchronize()
+    srv = Server(budget_bytes=4e9, max_slots=4)
+    outs = [torch.empty(g.vol_shape, device="cuda") for g, _ in reqs]
+    tickets = [srv.submit(g, y, o, lam=0.05, iters=iters) for (g, y), o in zip(reqs, outs)]
+    srv.wait_all()
+    for t, o, s in zip(tickets, outs, solo):
+        done, status, _ = srv.poll(t)
+        assert done and status == 0, srv.poll(t)
+        assert torch.equal(o, s)
+    srv.close()
+
+
 def test_budget_serialises_when_tight():
     from paper_1001_0599_amd.serving import Server
     reqs = _requests()[:3]
