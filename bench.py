@@ -503,7 +503,7 @@ def main():
         kernels_only()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (it times the one-GPU "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (it times the one-GPU "
               "share of the workload); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -110,8 +110,8 @@ def lib():
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
-                raise ImportError("libcbct.so is not built (run paper_1001_0599_amd/build.py or "
-                                  "__graft_entry__.build()); there is no fallback path")
+                raise ImportError("libcbct.so is not built (run python paper_1001_0599_amd/build.py); "
+                                  "there is no fallback path")
             L = C.CDLL(LIB_PATH)
             for name, res, args in _SIG:
                 fn = getattr(L, name)

@@ -100,6 +100,30 @@ def test_gated_loop_equals_host_driven_loop():
         assert torch.equal(u1, u2), t
 
 
+@pytest.mark.parametrize("shape", [(12, 12, 8), (40, 24, 16)])
+def test_step2_reports_nonfinite_energies(shape):
+    """A NaN in the ROF input reaches the energies; Step 2 ends and reports CBCT_ERR_NONFINITE on
+    each path: one work-group (up to 4096 voxels), gated chains, and the host-driven loop (a
+    replayed decision selects it); a whole solve with a NaN in its projections fails the same way."""
+    from paper_1001_0599_amd._lib import CbctError
+    g = dataclasses.replace(G1, nx=shape[0], ny=shape[1], nz=shape[2])
+    plan = _plan(g)
+    gv = 0.02 * S.random_volume(g, 13)
+    gv[shape[2] // 2, shape[1] // 2, shape[0] // 2] = np.nan
+    for replay in (None, [(0, 1)]):
+        announce("non-finite Step 2, %s, replay %s" % (shape, replay))
+        with pytest.raises(CbctError) as e:
+            plan.tv_prox(to_gpu(gv), 0.05, 1.0, replay=replay)
+        assert e.value.status == 5, e.value
+    torch.cuda.synchronize()
+    y = np.array(S.random_projections(g, 14), dtype=np.float64)
+    y[0, g.nv // 2, g.nu // 2] = np.nan  # a central ray: it crosses the volume
+    with pytest.raises(CbctError) as e:
+        plan.reconstruct(to_gpu(y), lam=0.05, iters=[2])
+    assert e.value.status == 5, e.value
+    torch.cuda.synchronize()
+
+
 # A decision that differs from the oracle's is an FP32 tie only when the oracle's own margin at it
 # is below this (relative to E_0): the GPU's energies are FP64 sums of FP32 values, within about
 # 1e-7 relative of the oracle's on the same decision sequence, so a genuine tie sits an order of
