@@ -78,11 +78,11 @@ __device__ __forceinline__ void column_profiles(const float *__restrict__ src, l
     //   Z(c) = sum_j W_j hat(gamma (q_j - x_c)) = gamma (S2(x_{c+1}) - 2 S2(x_c) + S2(x_{c-1})),
     // since x_{c+1} - x_c = 1 / gamma is the hat's half-width; CG + 2 evaluations of S2 (one prefix
     // lookup each) serve the item's CG cells.  The FP64 prefix sums keep the cancellation harmless
-    // (|S2| is at most a few 1e5 times the row values).
-#ifndef CBCT_PROF_CG
-#define CBCT_PROF_CG 8
-#endif
-    constexpr int CG = CBCT_PROF_CG;
+    // (|S2| is at most a few 1e5 times the row values).  CG = 4: each lane stores one float4, so
+    // a wave's store covers 1 KB of consecutive profile floats; with CG = 8 (two float4 per lane,
+    // 16-byte pieces at a 32-byte stride per store, 1.25 instead of 1.5 evaluations per cell) a P^T
+    // at 512x512x64 / 40 views took 1.71-1.72 against 1.63 ms.
+    constexpr int CG = 4;
     const double beta = 0.5 * (double)(nz - 1);
     const int nq = (nz + CG - 1) / CG;
     const bool vec = (nz & 3) == 0;
