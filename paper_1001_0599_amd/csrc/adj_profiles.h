@@ -5,7 +5,7 @@
 // bilinear weights of the sample's transverse position and Lz the linear weight of the row's z
 // index s_kj = gamma_k q_j + (nz-1)/2.  Hence
 //   (P^T y)_abc = sum_t sum_i sum_k Lx(a) Ly(b) Z_tik(c),  Z_tik(c) = sum_j w_ij y_tji hat(s_kj - c).
-// The work-group forms FP64 prefix sums A[J] = sum_{j<J} W_j and B[J] = sum_{j<J} q_j W_j (W = w y)
+// The work-group forms FP64 prefix sums A[J] = sum_{j<J} W_j and B[J] = sum_{j<J} j W_j (W = w y)
 // over the column's rows and writes Z_tik(c) for every sample k inside the grid's support and
 // every cell c, each in O(1): the rows with s in [c-1, c) and [c, c+1) are the index ranges
 // [J(c-1), J(c)) and [J(c), J(c+1)) with J(x) = ceil((x - (nz-1)/2)/gamma_k + (nv-1)/2), and the
@@ -18,14 +18,13 @@
 #include "cbct_internal.h"
 
 // The column's detector values are src[j * stride], j = 0 .. nv-1 (a projection column in global
-// memory).  PREWEIGHTED: they are
-// already w_ij * y.  Dynamic LDS: (nv + 1 + zk_max) double2 when gb_lds, else (nv + 1).  Any block
-// size that is a multiple of 64, up to 1024.
+// memory).  PREWEIGHTED: they are already w_ij * y.  ab: the LDS table, (nv + 1 + zk_max) double2
+// when gb_lds, else (nv + 1).  Any block size that is a multiple of 64, up to 1024.
 template <bool PREWEIGHTED>
 __device__ __forceinline__ void column_profiles(const float *__restrict__ src, long stride, const ColParams cp,
                                                 const ZIndex zi, int nv, int nz, float pv, bool gb_lds,
-                                                float *__restrict__ Z) {
-    extern __shared__ double2 ab[];  // [nv + 1]: (A, B), then [max nk] per-sample constants
+                                                float *__restrict__ Z, double2 *ab) {
+    // ab: [nv + 1] (A, B), then [max nk] per-sample constants
     __shared__ double wtot[16][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (int)blockDim.x >> 6;
     const float iv = 0.5f * (float)(nv - 1);
@@ -45,7 +44,7 @@ __device__ __forceinline__ void column_profiles(const float *__restrict__ src, l
                 w *= cp.wsc * sqrtf(fmaf(v, v, cp.r2));
             }
             wa = (double)w;
-            wb = (double)w * (double)q;
+            wb = (double)w * (double)j;  // exact: a float times an integer below 2^24
         }
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -73,7 +72,7 @@ __device__ __forceinline__ void column_profiles(const float *__restrict__ src, l
         __syncthreads();
     }
     // profiles: items (sample, CG consecutive cells), cells fastest.  With x_c = (c - beta) / gamma
-    // (cell c in row units) and S2(x) = sum_{q_j < x} W_j (x - q_j) = x A(J) - B(J), J = ceil(x + iv)
+    // + iv (cell c in row-index units) and S2(x) = sum_{j < x} W_j (x - j) = x A(J) - B(J), J = ceil(x)
     // the rows below x (clamped to [0, nv]), the hat sum is a second difference:
     //   Z(c) = sum_j W_j hat(gamma (q_j - x_c)) = gamma (S2(x_{c+1}) - 2 S2(x_c) + S2(x_{c-1})),
     // since x_{c+1} - x_c = 1 / gamma is the hat's half-width; CG + 2 evaluations of S2 (one prefix
@@ -97,11 +96,12 @@ __device__ __forceinline__ void column_profiles(const float *__restrict__ src, l
         }
         __syncthreads();
     }
-    // items it = tid + m * blockDim: (kk, cq) advance by (dkk, dcq) with one carry
+    // items it = tid + m * blockDim: (kk, cq) advance by (dkk, dcq) with one carry (none when nq
+    // divides the block size: then every thread keeps its cell group)
     const int dkk = (int)blockDim.x / nq, dcq = (int)blockDim.x - dkk * nq;
     int kk = tid / nq, cq = tid - kk * nq;
     for (; kk < zi.nk; kk += dkk, cq += dcq) {
-        if (cq >= nq) {
+        if (dcq != 0 && cq >= nq) {
             cq -= nq;
             if (++kk >= zi.nk) break;
         }
@@ -117,11 +117,12 @@ __device__ __forceinline__ void column_profiles(const float *__restrict__ src, l
             base = (double)iv - beta * ig;
         }
         double s2[CG + 2];
+        double xr = fma((double)(cg0 - 1), ig, base);  // x of cell cg0 - 1 (row-index units)
 #pragma unroll
         for (int q = 0; q < CG + 2; q++) {
-            const double xr = fma((double)(cg0 - 1 + q), ig, base);  // x_c + iv (row index units)
-            const double2 p = ab[(int)fmin(fmax(ceil(xr), 0.0), (double)nv)];
-            s2[q] = fma(xr - (double)iv, p.x, -p.y);
+            if (q) xr += ig;
+            const double2 p = ab[min(max((int)ceil(xr), 0), nv)];
+            s2[q] = fma(xr, p.x, -p.y);
         }
         float o[CG];
 #pragma unroll

@@ -34,11 +34,12 @@ __global__ void __launch_bounds__(256)
     k_adj_profiles(const float *__restrict__ proj, const ColParams *__restrict__ cols,
                    const ZIndex *__restrict__ zix, int nu, int nv, int nz, float pv, bool gb_lds,
                    float *__restrict__ Z) {
+    extern __shared__ double2 ab[];
     // adjacent columns share the cache lines of their projection rows: keep them on one XCD
     const int w = cbct_xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
     const int i = w % nu, view = w / nu;
     const long col = (long)view * nu + i;
-    column_profiles<PREWEIGHTED>(proj + (long)view * nv * nu + i, nu, cols[col], zix[col], nv, nz, pv, gb_lds, Z);
+    column_profiles<PREWEIGHTED>(proj + (long)view * nv * nu + i, nu, cols[col], zix[col], nv, nz, pv, gb_lds, Z, ab);
 }
 
 // ---------------------------------------------------------------------------- pass 2
