@@ -305,28 +305,28 @@ __global__ void __launch_bounds__(256)
                 {
                     constexpr int PER = (GS_ROWS * GS_Q + 255) / 256;
                     const int items = nrows * GS_Q;  // > 0
-                    float4 v[PER];
+                    static_assert(PER == 10, "the asm statement below lists the batch's ten loads");
+                    v4f v[PER];
+                    const float *zq = Z + 4 * (tid & (GS_Q - 1));  // this thread's float4 slot of a row
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
-                        // items past the batch load its last row again (no branch between the loads)
-                        const int it = min(tid + 256 * j, items - 1);
+                        // item tid + 256 j: row (tid >> GS_QS) + j 256 / GS_Q; items past the batch load
+                        // its last row again (no branch between the loads)
+                        const int r = min((tid >> GS_QS) + j * (256 >> GS_QS), nrows - 1);
                         // a non-temporal load: these profile lines are read once, from HBM
-                        const v4f t = __builtin_nontemporal_load(
-                            reinterpret_cast<const v4f *>(Z + rowsrc[it >> GS_QS] + 4 * (it & (GS_Q - 1))));
-                        v[j] = make_float4(t.x, t.y, t.z, t.w);
+                        v[j] = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(zq + rowsrc[r]));
                     }
-                    // all loads in flight before the first store: an empty asm statement consumes
-                    // every loaded word here, so the compiler cannot sink (or split) each load
-                    // down to its store; idle slots store into the spill row
-                    float dep = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < PER; j++) dep += (v[j].x + v[j].y) + (v[j].z + v[j].w);
-                    asm volatile("" ::"v"(dep));
+                    // all loads in flight before the first store: an empty asm statement takes every
+                    // loaded vector as an operand (no instructions), so the compiler cannot sink (or
+                    // split) each load down to its store; idle slots store into the spill row
+                    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]),
+                                 "v"(v[7]), "v"(v[8]), "v"(v[9]));
+                    v4f *zsv = reinterpret_cast<v4f *>(zs);
 #pragma unroll
                     for (int j = 0; j < PER; j++) {
                         const int it = tid + 256 * j;
                         const int r = it < items ? (it >> GS_QS) : GS_ROWS;
-                        zs[r * GS_PITCH + (it & (GS_Q - 1))] = v[j];
+                        zsv[r * GS_PITCH + (it & (GS_Q - 1))] = v[j];
                     }
                 }
                 __syncthreads();
