@@ -20,7 +20,9 @@
 //     sample's profile segment (float4 loads, shared through the caches by neighbouring voxels).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
+#include <vector>
 
 #include "cbct_internal.h"
 #include "adj_profiles.h"
@@ -201,25 +203,34 @@ struct GsCol {
 };
 static_assert(sizeof(GsCol) == 48, "GsCol layout");
 
-// With view groups (vgroups > 1) the work-group of group g covers views [g vper, (g+1) vper) and
-// writes its sums to part[g]; k_adj_combine adds the groups in order.
 template <int GS_TZ, int GS_ROWS>
-__global__ void __launch_bounds__(256)
-    k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
-                        const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
-                        int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
-                        float *__restrict__ part) {
-    constexpr int GS_Q = GS_TZ / 4;                 // float4 slots per profile row
-    constexpr int GS_QS = GS_TZ == 64 ? 4 : 3;      // log2(GS_Q)
-    constexpr int GS_PITCH = GS_Q + 1;              // one pad slot per staged row against bank conflicts
-    __shared__ float4 zs[(GS_ROWS + 1) * GS_PITCH];  // + one spill row for the staging's idle slots
-    __shared__ GsCol ci[GS_CC];
-    __shared__ int cnt[GS_CC + 1];  // exclusive row offsets of the chunk's columns; cnt[nc] = rows
-    __shared__ long rowsrc[GS_ROWS];  // profile offset of each staged row
+struct GatherLds {
+    static constexpr int PITCH = GS_TZ / 4 + 1;  // float4 slots per staged row (one pad slot)
+    float4 zs[(GS_ROWS + 1) * PITCH];            // + one spill row for the staging's idle slots
+    GsCol ci[GS_CC];
+    int cnt[GS_CC + 1];    // exclusive row offsets of the chunk's columns; cnt[nc] = rows
+    long rowsrc[GS_ROWS];  // profile offset of each staged row
+};
 
-    int tx, ty, tzg;
-    tile_of(tx, ty, tzg);
-    const int nzt = A.nz / GS_TZ, tz = tzg % nzt, grp = tzg / nzt;
+// Tile (tx, ty, tz) of view group grp: the views [grp vper, (grp+1) vper).  With view groups
+// (vgroups > 1) the sums go to part[grp] (k_adj_combine adds the groups in order); else
+// out = fbase - kappa * sum (or the sum), and out2 the same when given.
+template <int GS_TZ, int GS_ROWS>
+__device__ __forceinline__ void gather_staged_body(GatherLds<GS_TZ, GS_ROWS> &lds, const float *__restrict__ Z,
+                                                   const ZIndex *__restrict__ zix, const ColParams *__restrict__ cols,
+                                                   const ViewParams *__restrict__ views, const AdjArgs &A, int tx,
+                                                   int ty, int tz, int grp, int vgroups, int vper,
+                                                   const float *__restrict__ fbase, float kappa,
+                                                   float *__restrict__ out, float *__restrict__ out2,
+                                                   float *__restrict__ part) {
+    constexpr int GS_Q = GS_TZ / 4;             // float4 slots per profile row
+    constexpr int GS_QS = GS_TZ == 64 ? 4 : 3;  // log2(GS_Q)
+    constexpr int GS_PITCH = GS_Q + 1;
+    float4 *zs = lds.zs;
+    GsCol *ci = lds.ci;
+    int *cnt = lds.cnt;
+    long *rowsrc = lds.rowsrc;
+
     const int v_begin = grp * vper, v_end = min(A.nviews, v_begin + vper);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int a0 = tx * ADJ_TX, b0 = ty * ADJ_TY, c0 = tz * GS_TZ;
@@ -374,10 +385,30 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int q = 0; q < GS_TZ; q++) {
             const long idx = ((long)(c0 + q) * A.ny + b) * A.nx + a;
-            if (vgroups > 1) part[grp * nvox + idx] = acc[q];
-            else out[idx] = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
+            if (vgroups > 1) {
+                part[grp * nvox + idx] = acc[q];
+            } else {
+                const float o = fbase ? fmaf(-kappa, acc[q], fbase[idx]) : acc[q];
+                out[idx] = o;
+                if (out2) out2[idx] = o;
+            }
         }
     }
+}
+
+// grid (tiles x, tiles y, (nz / GS_TZ) * vgroups)
+template <int GS_TZ, int GS_ROWS>
+__global__ void __launch_bounds__(256)
+    k_adj_gather_staged(const float *__restrict__ Z, const ZIndex *__restrict__ zix,
+                        const ColParams *__restrict__ cols, const ViewParams *__restrict__ views, AdjArgs A,
+                        int vgroups, int vper, const float *__restrict__ fbase, float kappa, float *__restrict__ out,
+                        float *__restrict__ out2, float *__restrict__ part) {
+    __shared__ GatherLds<GS_TZ, GS_ROWS> lds;
+    int tx, ty, tzg;
+    tile_of(tx, ty, tzg);
+    const int nzt = A.nz / GS_TZ;
+    gather_staged_body<GS_TZ, GS_ROWS>(lds, Z, zix, cols, views, A, tx, ty, tzg % nzt, tzg / nzt, vgroups, vper, fbase,
+                                       kappa, out, out2, part);
 }
 
 // out = sum of the view groups' partial volumes (in group order), or fbase - kappa * that sum;
@@ -391,6 +422,92 @@ __global__ void __launch_bounds__(256) k_adj_combine(const float *__restrict__ p
         const float v = fbase ? fmaf(-kappa, s, fbase[i]) : s;
         out[i] = v;
         if (out2) out2[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------- batched (serving)
+// Several requests in one launch: request q owns work-groups [wg0[q], wg0[q+1]) and each runs the
+// solo kernel's body on that request's buffers, so the results are bitwise those of solo launches.
+__device__ __forceinline__ int batch_item(const int *wg0, int n) {
+    int r = 0;
+    while (r + 1 < n && (int)blockIdx.x >= wg0[r + 1]) r++;
+    return r;
+}
+
+struct BPrItem {  // profiles: one work-group per (view, column)
+    const float *proj;
+    const ColParams *cols;
+    const ZIndex *zix;
+    float *Z;
+    int nu, nv, nz, gb_lds;
+    float pv;
+};
+struct BPr {
+    int n;
+    int wg0[CBCT_MAXB + 1];
+    BPrItem it[CBCT_MAXB];
+};
+__global__ void __launch_bounds__(256) k_adj_profiles_b(BPr B) {
+    extern __shared__ double2 ab[];
+    const int r = batch_item(B.wg0, B.n);
+    const BPrItem &it = B.it[r];
+    const int w = (int)blockIdx.x - B.wg0[r];
+    const int i = w % it.nu, view = w / it.nu;
+    const long col = (long)view * it.nu + i;
+    column_profiles<true>(it.proj + (long)view * it.nv * it.nu + i, it.nu, it.cols[col], it.zix[col], it.nv, it.nz,
+                          it.pv, it.gb_lds != 0, it.Z, ab);
+}
+
+struct BGaItem {  // staged gather: one work-group per (tile, view group)
+    const float *Z;
+    const ZIndex *zix;
+    const ColParams *cols;
+    const ViewParams *views;
+    const float *fbase;
+    float *out, *out2, *part;
+    AdjArgs A;
+    int ntx, nty, vgroups, vper;
+    float kappa;
+};
+struct BGa {
+    int n;
+    int wg0[CBCT_MAXB + 1];
+    BGaItem it[CBCT_MAXB];
+};
+static_assert(sizeof(BGa) <= 4096, "batched gather arguments");
+__global__ void __launch_bounds__(256) k_adj_gather_staged_b(BGa B) {
+    __shared__ GatherLds<32, GS_ROWS32> lds;
+    const int r = batch_item(B.wg0, B.n);
+    const BGaItem &it = B.it[r];
+    const int w = (int)blockIdx.x - B.wg0[r];
+    const int nzt = it.A.nz / 32, tzg = w / (it.ntx * it.nty), t2 = w - tzg * it.ntx * it.nty;
+    gather_staged_body<32, GS_ROWS32>(lds, it.Z, it.zix, it.cols, it.views, it.A, t2 % it.ntx, t2 / it.ntx, tzg % nzt,
+                                      tzg / nzt, it.vgroups, it.vper, it.fbase, it.kappa, it.out, it.out2, it.part);
+}
+
+struct BCoItem {  // view-group sums: nb work-groups striding over the request's voxels
+    const float *part;
+    const float *fbase;
+    float *out, *out2;
+    long n;
+    int vgroups;
+    float kappa;
+};
+struct BCo {
+    int n;
+    int wg0[CBCT_MAXB + 1];
+    BCoItem it[CBCT_MAXB];
+};
+__global__ void __launch_bounds__(256) k_adj_combine_b(BCo B) {
+    const int r = batch_item(B.wg0, B.n);
+    const BCoItem &it = B.it[r];
+    const long w = (long)blockIdx.x - B.wg0[r], nb = B.wg0[r + 1] - B.wg0[r];
+    for (long i = w * blockDim.x + threadIdx.x; i < it.n; i += nb * blockDim.x) {
+        float s = it.part[i];
+        for (int g = 1; g < it.vgroups; g++) s += it.part[g * it.n + i];
+        const float v = it.fbase ? fmaf(-it.kappa, s, it.fbase[i]) : s;
+        it.out[i] = v;
+        if (it.out2) it.out2[i] = v;
     }
 }
 
@@ -445,16 +562,15 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
         float *part = Zws + L.adj_part_off;
         dim3 grid((L.nx + ADJ_TX - 1) / ADJ_TX, (L.ny + ADJ_TY - 1) / ADJ_TY, (nz / tzs) * vg);
         hipLaunchKernelGGL((k_adj_gather_staged<32, GS_ROWS32>), grid, dim3(ADJ_TX * ADJ_TY), 0, s, Zws, L.d_zix,
-                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, part);
+                           L.d_cols, L.d_views, L.adj, vg, vper, fbase, kappa, out, out2, part);
         LAUNCH_CHECK("k_adj_gather_staged");
         if (vg > 1) {
             const long n = L.nvox();
             const int nb = (int)std::min<long>((n + 255) / 256, 4096);
             hipLaunchKernelGGL(k_adj_combine, dim3(nb), dim3(256), 0, s, part, vg, n, fbase, kappa, out, out2);
             LAUNCH_CHECK("k_adj_combine");
-            return CBCT_OK;
         }
-        return copy_out2();
+        return CBCT_OK;  // one view group: the gather wrote out2
     }
     // other depths: per-lane gather, z cells per thread up to 64 (the window and weight work per
     // voxel column and view is shared by all its cells), views split into groups on small grids
@@ -475,4 +591,75 @@ cbct_status cbct_launch_adjoint(const Level &L, const float *proj, const float *
         return CBCT_OK;
     }
     return copy_out2();
+}
+
+cbct_status cbct_launch_adjoint_batch(const AdjReq *r, int n, hipStream_t s, int *launches, int *items) {
+    int nl = 0, ni = 0;
+    cbct_status st;
+    std::vector<int> staged;
+    for (int q = 0; q < n; q++) {
+        if (cbct_adj_staged_tz(r[q].L->nz)) {
+            staged.push_back(q);
+            continue;
+        }
+        // the per-lane gather: a solo launch sequence
+        if ((st = cbct_launch_adjoint(*r[q].L, r[q].proj, r[q].fbase, r[q].kappa, r[q].out, r[q].Zws, s, true,
+                                      r[q].out2)))
+            return st;
+        nl += 3;
+        ni += 3;
+    }
+    for (size_t q0 = 0; q0 < staged.size(); q0 += CBCT_MAXB) {
+        const int m = (int)std::min<size_t>(CBCT_MAXB, staged.size() - q0);
+        BPr P{};
+        BGa G{};
+        BCo C{};
+        size_t lds = 0;
+        int wp = 0, wg = 0, wc = 0;
+        for (int j = 0; j < m; j++) {
+            const AdjReq &a = r[staged[q0 + j]];
+            const Level &L = *a.L;
+            // the same LDS table choice as a solo launch
+            size_t l1 = sizeof(double2) * (L.nv + 1 + L.zk_max);
+            const bool gb = l1 <= 64 * 1024;
+            if (!gb) l1 = sizeof(double2) * (L.nv + 1);
+            lds = std::max(lds, l1);
+            P.it[j] = BPrItem{a.proj, L.d_cols, L.d_zix, a.Zws, L.nu, L.nv, L.nz, gb ? 1 : 0, (float)L.pv};
+            P.wg0[j] = wp;
+            wp += L.nu * L.nviews;
+            const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
+            const int ntx = (L.nx + ADJ_TX - 1) / ADJ_TX, nty = (L.ny + ADJ_TY - 1) / ADJ_TY;
+            float *part = a.Zws + L.adj_part_off;
+            G.it[j] = BGaItem{a.Zws, L.d_zix, L.d_cols, L.d_views, a.fbase, a.out, a.out2, part, L.adj,
+                              ntx, nty, vg, vper, a.kappa};
+            G.wg0[j] = wg;
+            wg += ntx * nty * (L.nz / 32) * vg;
+            if (vg > 1) {
+                const long nvox = L.nvox();
+                C.it[C.n] = BCoItem{part, a.fbase, a.out, a.out2, nvox, vg, a.kappa};
+                C.wg0[C.n] = wc;
+                wc += (int)std::min<long>((nvox + 255) / 256, 4096);
+                C.n++;
+            }
+        }
+        P.n = G.n = m;
+        P.wg0[m] = wp;
+        G.wg0[m] = wg;
+        C.wg0[C.n] = wc;
+        hipLaunchKernelGGL(k_adj_profiles_b, dim3(wp), dim3(256), lds, s, P);
+        LAUNCH_CHECK("k_adj_profiles_b");
+        hipLaunchKernelGGL(k_adj_gather_staged_b, dim3(wg), dim3(ADJ_TX * ADJ_TY), 0, s, G);
+        LAUNCH_CHECK("k_adj_gather_staged_b");
+        nl += 2;
+        ni += 2 * m;
+        if (C.n) {
+            hipLaunchKernelGGL(k_adj_combine_b, dim3(wc), dim3(256), 0, s, C);
+            LAUNCH_CHECK("k_adj_combine_b");
+            nl++;
+            ni += C.n;
+        }
+    }
+    if (launches) *launches = nl;
+    if (items) *items = ni;
+    return CBCT_OK;
 }

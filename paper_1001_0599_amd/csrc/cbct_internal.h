@@ -253,6 +253,19 @@ struct FwdReq {
 // residual P of several requests; requests whose projector configuration differs from the first
 // one's go to further launches (same stream)
 cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s);
+struct AdjReq {
+    const Level *L;
+    const float *proj;   // w * (P f - Y) (preweighted)
+    const float *fbase;  // out = fbase - kappa P^T proj
+    float kappa;
+    float *out, *out2;   // out2: a second copy of out (may be null)
+    float *Zws;          // the request's adjoint workspace
+};
+// Step 1 of several requests (cbct_launch_adjoint with preweighted input): one launch each for
+// the profiles, the staged gathers and the view-group sums; requests whose depth is not a
+// multiple of 32 get launches of their own.  *launches: the number of launches made, *items: the
+// number of (request, launch) pairs they carried.
+cbct_status cbct_launch_adjoint_batch(const AdjReq *r, int n, hipStream_t s, int *launches, int *items);
 
 // multigrid transfers and small vector kernels
 cbct_status cbct_launch_prolong(const Level &coarse, const float *c, float *f, hipStream_t s);

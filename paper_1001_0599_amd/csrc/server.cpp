@@ -455,10 +455,15 @@ cbct_status round_(cbct_server *s, std::vector<Request *> &act, hipStream_t st_)
     s->batched_launches++;
     s->batched_items += n;
     // Step 1: g = f - kappa P^T r, also into the ROF start u
-    for (Request *r : act) {
-        const Level &L = r->pe->plan->lv[r->level];
-        if ((st = cbct_launch_adjoint(L, r->b.r, r->b.f, r->kappa, r->b.g, r->b.z, st_, true, r->b.u))) return st;
+    std::vector<AdjReq> ad(n);
+    for (int q = 0; q < n; q++) {
+        Request *r = act[q];
+        ad[q] = AdjReq{&r->pe->plan->lv[r->level], r->b.r, r->b.f, r->kappa, r->b.g, r->b.u, r->b.z};
     }
+    int nl = 0, ni = 0;
+    if ((st = cbct_launch_adjoint_batch(ad.data(), n, st_, &nl, &ni))) return st;
+    s->batched_launches += nl;
+    s->batched_items += ni;
     // Step 2: the small requests ran their loop in one work-group above; the others run gated
     // steps in shared launches (see cbct_launch_rof_step_gated_batch), AHEAD steps in front of
     // the decisions, and leave the batch when a decision ends their loop
