@@ -34,7 +34,8 @@ struct SidCol {
     float ex, ey;    // unit direction, source to detector
     float iex, iey;  // 1/ex, 1/ey (0 when |e| <= 1e-12: the line runs parallel to those planes)
     float t0, lxy, ilxy;
-    float pad[3];
+    float t0lo, lxylo;  // t0 - (double)t0 and lxy - (double)lxy: the FP64 values as float pairs
+    float pad;
 };
 static_assert(sizeof(SidCol) == 48, "SidCol layout");
 

@@ -110,6 +110,8 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
             sc.iey = std::fabs(my) > 1e-12 ? (float)(1.0 / my) : 0.0f;
             sc.t0 = (float)tau_c;
             sc.lxy = (float)r;
+            sc.t0lo = (float)(tau_c - (double)sc.t0);
+            sc.lxylo = (float)(r - (double)sc.lxy);
             sc.ilxy = (float)(1.0 / r);
             ColParams &c = cols[(size_t)v * L.nu + i];
             const double fx0 = cx / L.hx + 0.5 * (L.nx - 1), fy0 = cy / L.hy + 0.5 * (L.ny - 1);

@@ -4,8 +4,9 @@
 //
 // Parameterisation.  All rays of one detector column lie in one vertical plane and share its
 // transverse (xy) line.  tau is the transverse distance along that line from C, the line's closest
-// approach to the rotation axis (|tau| stays within the grid's half diagonal, so FP32 crossing
-// parameters are accurate to ~1e-5 mm); the source sits at tau = -t0, the detector at lxy - t0.
+// approach to the rotation axis (|tau| stays within the grid's half diagonal, so float crossing
+// parameters are accurate to ~1e-5 mm; the z crossings, which involve the source distance, are
+// formed in FP64 first); the source sits at tau = -t0, the detector at lxy - t0.
 // The ray of detector height v has z(tau) = (tau + t0) v / lxy and 3-D length per unit tau of
 // sqrt(1 + (v / lxy)^2).  Cubes are half-open on their upper faces (a ray lying in a face plane
 // belongs to the cube above it).
@@ -31,6 +32,7 @@ constexpr int SID_TZ = 8;  // z cells per thread of the gather
 struct SidArgs {
     int nx, ny, nz, nu, nv, nviews;
     float hx, hy, hz, pu, pv, sad, sdd;
+    double hzd, pvd;  // hz and pv in FP64 (the z crossings)
 };
 
 // plane p (0 .. n) of an axis with n cells of pitch h centred on the origin
@@ -56,16 +58,36 @@ __device__ __forceinline__ void sid_slab(float c, float ie, int p0, int p1, int 
 // detector height of row j
 __device__ __forceinline__ float sid_row_v(int j, const SidArgs &A) { return ((float)j - 0.5f * (float)(A.nv - 1)) * A.pv; }
 
-// tau at which a ray with dz/dtau = v / lxy (ikz = lxy / v) crosses z plane p
-__device__ __forceinline__ float sid_zcross(int p, const SidArgs &A, float ikz, float t0) {
-    return sid_plane(p, A.nz, A.hz) * ikz - t0;
+// z crossings in FP64.  The ray of detector height v rises v / lxy per unit of tau from the source
+// at tau = -t0, so it crosses z plane p at tau = z_p lxy / v - t0.  With t0 (about 1e3 mm) and
+// lxy taken from the table's float pairs and z_p, v in FP64, that tau is exact up to its one
+// rounding to float (|tau| stays within the grid's half diagonal: ~1e-5 mm), where float
+// arithmetic left ~1e-4 mm (the 6e-8 relative error of lxy / v carried over the source
+// distance).  Forward and transpose kernels use these same expressions.
+__device__ __forceinline__ double sid_t0(const SidCol &c) { return (double)c.t0 + (double)c.t0lo; }
+
+// lxy / v of row j (0 for v = 0: the ray stays in one z cell)
+__device__ __forceinline__ double sid_ikz(const SidCol &c, const SidArgs &A, int j) {
+    const double v = ((double)j - 0.5 * (double)(A.nv - 1)) * A.pvd;
+    return v != 0.0 ? ((double)c.lxy + (double)c.lxylo) / v : 0.0;
+}
+
+// tau at which the ray with lxy / v = ikz crosses z plane p
+__device__ __forceinline__ float sid_zcross(int p, const SidArgs &A, double ikz, double t0) {
+    return (float)fma(((double)p - 0.5 * (double)A.nz) * A.hzd, ikz, -t0);
 }
 
 // tau of the next z crossing of a lane in cell cz moving by sz (+-1, 0): none once it has left the grid
-__device__ __forceinline__ float sid_znext(int cz, int sz, const SidArgs &A, float ikz, float t0) {
+__device__ __forceinline__ float sid_znext(int cz, int sz, const SidArgs &A, double ikz, double t0) {
     if (sz > 0) return cz < A.nz ? sid_zcross(cz + 1, A, ikz, t0) : SID_INF;
     if (sz < 0) return cz >= 0 ? sid_zcross(cz, A, ikz, t0) : SID_INF;
     return SID_INF;
+}
+
+// z cell of that ray at tau, clamped to [-1, nz] (v = 0: the cell of z = 0)
+__device__ __forceinline__ int sid_zcell(float tau, const SidArgs &A, double ikz, double t0) {
+    const double z = ikz != 0.0 ? ((double)tau + t0) / ikz : 0.0;
+    return (int)fmin(fmax(floor(z / A.hzd + 0.5 * (double)A.nz), -1.0), (double)A.nz);
 }
 
 __global__ void __launch_bounds__(256) k_siddon_forward(const float *__restrict__ vol_t, const SidCol *__restrict__ cols,
@@ -93,9 +115,9 @@ __global__ void __launch_bounds__(256) k_siddon_forward(const float *__restrict_
         float tyn = c.iey != 0.0f ? (sid_plane(b + (sy > 0), A.ny, A.hy) - c.cy) * c.iey : SID_INF;
         // z state of this lane's ray
         const int sz = v > 0.0f ? 1 : (v < 0.0f ? -1 : 0);
-        const float ikz = v != 0.0f ? c.lxy * (1.0f / v) : 0.0f;
-        int cz = min(max(sid_cell((tin + c.t0) * kz, A.nz, A.hz), -1), A.nz);
-        float tzn = sid_znext(cz, sz, A, ikz, c.t0);
+        const double ikz = sid_ikz(c, A, j), t0d = sid_t0(c);
+        int cz = sid_zcell(tin, A, ikz, t0d);
+        float tzn = sid_znext(cz, sz, A, ikz, t0d);
         float t = tin;
         for (;;) {
             const float tn = fminf(fminf(txn, tyn), tout);
@@ -107,7 +129,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward(const float *__restrict_
                     if ((unsigned)cz < (unsigned)A.nz) acc = fmaf(col[cz], e - tt, acc);
                     tt = e;
                     cz += sz;
-                    tzn = sid_znext(cz, sz, A, ikz, c.t0);
+                    tzn = sid_znext(cz, sz, A, ikz, t0d);
                 }
                 if ((unsigned)cz < (unsigned)A.nz) acc = fmaf(col[cz], tn - tt, acc);
                 t = tn;
@@ -186,8 +208,8 @@ __global__ void __launch_bounds__(256) k_siddon_gather(const float *__restrict__
                         const float v = sid_row_v(j, A);
                         float lo, hi;
                         if (v != 0.0f) {
-                            const float ikz = c.lxy * (1.0f / v);
-                            const float t1 = sid_zcross(c0 + k, A, ikz, c.t0), t2 = sid_zcross(c0 + k + 1, A, ikz, c.t0);
+                            const double ikz = sid_ikz(c, A, j), t0d = sid_t0(c);
+                            const float t1 = sid_zcross(c0 + k, A, ikz, t0d), t2 = sid_zcross(c0 + k + 1, A, ikz, t0d);
                             lo = fminf(t1, t2);
                             hi = fmaxf(t1, t2);
                         } else {
@@ -353,18 +375,18 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
         const float ihx = 1.0f / A.hx, ihy = 1.0f / A.hy;
 
         // rays: pair p = row j (v <= 0) and its mirror nv - 1 - j; z state of row j
-        float ikz[NPT], t0r[NPT];
+        double ikz[NPT];
+        const double t0d = sid_t0(c);
         int cz[NPT], szr[NPT];
         float tzn[NPT];
 #pragma unroll
         for (int p = 0; p < NPT; p++) {
-            const int j = tid + p * nthr;
-            const float v = sid_row_v(min(j, npairs - 1), A);
+            const int j = min(tid + p * nthr, npairs - 1);
+            const float v = sid_row_v(j, A);
             szr[p] = v > 0.0f ? 1 : (v < 0.0f ? -1 : 0);
-            ikz[p] = v != 0.0f ? c.lxy * (1.0f / v) : 0.0f;
-            t0r[p] = tin;
-            cz[p] = min(max(sid_cell((tin + c.t0) * (v * c.ilxy), A.nz, A.hz), -1), A.nz);
-            tzn[p] = sid_znext(cz[p], szr[p], A, ikz[p], c.t0);
+            ikz[p] = sid_ikz(c, A, j);
+            cz[p] = sid_zcell(tin, A, ikz[p], t0d);
+            tzn[p] = sid_znext(cz[p], szr[p], A, ikz[p], t0d);
         }
         const int sc = ((KP + nw - 1) / nw + 7) & ~7;
         const int ka = min(wave * sc, KP), kb = min(ka + sc, KP);
@@ -447,7 +469,7 @@ __global__ void __launch_bounds__(256) k_siddon_forward_runs(const float *__rest
                     const float2 e2 = tab[znc * S + k], e2m = tab[znmc * S + k];
                     qa = fmaf(e2.y, dt, e2.x);
                     qam = fmaf(e2m.y, dt, e2m.x);
-                    tz = sid_znext(z, szr[p], A, ikz[p], c.t0);
+                    tz = sid_znext(z, szr[p], A, ikz[p], t0d);
                 }
                 cz[p] = z;
                 tzn[p] = tz;
@@ -510,8 +532,8 @@ __global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ 
     const int nv = A.nv, nz = A.nz;
     float *Af = ldsf;                // [nv + 1]: prefix of w y
     float *wyf = Af + nv + 1;        // [nv]: w y
-    float *ivf = wyf + nv;           // [nv]: lxy / v (0 for v = 0)
-    float *pst = ivf + nv;           // [kmax + 1]
+    double *ivd = reinterpret_cast<double *>(wyf + nv + 1);  // [nv] (8-byte aligned): lxy / v, 0 for v = 0
+    float *pst = reinterpret_cast<float *>(ivd + nv);  // [kmax + 1]
     float *stg = pst + kmax + 1;     // [4][64][SPC + 1]
     const int vc = cbct_xcd_remap(blockIdx.x, gridDim.x);
     const int view = vc / A.nu, i = vc - view * A.nu;
@@ -527,7 +549,7 @@ __global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ 
     for (int j = tid; j < nv; j += nthr) {
         const float v = sid_row_v(j, A), kz = v * c.ilxy;
         wyf[j] = sqrtf(fmaf(kz, kz, 1.0f)) * proj[((long)view * nv + j) * A.nu + i];
-        ivf[j] = v != 0.0f ? c.lxy * (1.0f / v) : 0.0f;
+        ivd[j] = sid_ikz(c, A, j);
     }
     __syncthreads();
     if (tid < 64) {  // prefix over the rows in FP64, lane l taking rows [l R, (l + 1) R)
@@ -556,6 +578,7 @@ __global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ 
     const int K = sid_piece_list(c, A, tin, tout, kmax, pst, nullptr, tid, nthr, ln);
     if (tid == 0) rec[vc] = make_int4(ln.a0, ln.b0, K, 0);
     __syncthreads();
+    const double t0d = sid_t0(c);
     float *Zl = Z + (long)vc * kmax * nz;
     float *st = stg + wave * 64 * (SPC + 1);
     const float cj = 0.5f * (float)(nv - 1), ipv = 1.0f / A.pv;
@@ -575,7 +598,7 @@ __global__ void __launch_bounds__(256) k_sid_profiles(const float *__restrict__ 
             alo = Af[jl];
             part = 0.0f;
             for (int j = jl; j < jh; j++) {
-                const float th = fmaf(zp, ivf[j], -c.t0);  // the forward kernel's crossing of plane p
+                const float th = sid_zcross(p, A, ivd[j], t0d);  // the forward kernel's crossing of plane p
                 part = fmaf(wyf[j], fminf(fmaxf(zp > 0.0f ? th - ta : tb - th, 0.0f), len), part);
             }
         };
@@ -715,6 +738,7 @@ SidArgs sid_args(const Level &L) {
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
     A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
     A.sad = (float)L.sad; A.sdd = (float)L.sdd;
+    A.hzd = L.hz; A.pvd = L.pv;
     return A;
 }
 
@@ -784,7 +808,9 @@ size_t cbct_adjoint_siddon_ws_bytes(const Level &L) {
 cbct_status cbct_launch_adjoint_siddon(const Level &L, const float *proj, const float *fbase, float kappa, float *out,
                                        void *ws, hipStream_t s, float *out2) {
     const int kmax = L.nx + L.ny + 3;
-    const size_t lds = (size_t)(3 * L.nv + 1) * 4 + (size_t)(kmax + 1) * 4 + (size_t)4 * 64 * (16 + 1) * 4;
+    // Af, wyf (2 nv + 1 floats, padded to a whole double), ivd (nv doubles), pst, the staging blocks
+    const size_t lds = (size_t)(2 * L.nv + 2) * 4 + (size_t)L.nv * 8 + (size_t)(kmax + 1) * 4 +
+                       (size_t)4 * 64 * (16 + 1) * 4;
     if (lds <= 64 * 1024) {
         const size_t lines = (size_t)L.nviews * L.nu;
         float *Z = static_cast<float *>(ws);

@@ -257,15 +257,15 @@ def test_reconstruct_siddon_ragged():
 def test_reconstruct_siddon_tall_volume():
     """A tall thin volume (352 z cells): too many for the run-summing Siddon projector's
     tables, so the residual takes the per-ray walk and its separate residual pass.  Four views
-    of an 8 x 8 footprint make this solve ill-conditioned: the FP32 crossings (about 1e-5 off
-    the FP64 ones for these nearly horizontal rays) grow to 9e-5 in f after 3 outer iterations
-    and to 2e-3 after 5, where a Step 2 stop test then falls the other way; so 3 iterations."""
+    of an 8 x 8 footprint make this solve ill-conditioned and its rays nearly horizontal: with
+    float z crossings (up to 6e-4 off on single rays) f drifted to 2e-3 after 5 outer iterations
+    and a Step 2 stop test fell the other way; with the crossings in FP64 it stays within 1e-4."""
     g = dataclasses.replace(G1, nx=8, ny=8, nz=352, hx=2.0, hy=2.0, hz=0.25, nu=16, nv=2048, pu=2.0, pv=0.08,
                             n_views=4, angles=(0.1, 0.9, 2.0, 2.6))
     announce("reconstruct 8x8x352, 4 views x 2048 rows, Siddon pair (per-ray residual)")
     ph = S.make_phantom(g, 41)
     Y = S.poisson_log(S.analytic_projections(g, ph), 1e5, 42)
-    e, replayed, res, st = _compare_solve(g, Y, 0.05, [3], 1, projector=1)
+    e, replayed, res, st = _compare_solve(g, Y, 0.05, [5], 1, projector=1)
     assert e < 1e-3, (e, replayed)
     assert rel_l2(st["energy"], res.energy) < 1e-4
 
