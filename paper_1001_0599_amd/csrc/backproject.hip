@@ -439,7 +439,7 @@ struct BPrItem {  // profiles: one work-group per (view, column)
     const ColParams *cols;
     const ZIndex *zix;
     float *Z;
-    int nu, nv, nz, gb_lds;
+    int nu, nv, nz, nviews, gb_lds;
     float pv;
 };
 struct BPr {
@@ -451,7 +451,8 @@ __global__ void __launch_bounds__(256) k_adj_profiles_b(BPr B) {
     extern __shared__ double2 ab[];
     const int r = batch_item(B.wg0, B.n);
     const BPrItem &it = B.it[r];
-    const int w = (int)blockIdx.x - B.wg0[r];
+    const int w = cbct_batch_local(B.wg0[r], B.wg0[r + 1] - B.wg0[r]);
+    if (w >= it.nu * it.nviews) return;  // padding
     const int i = w % it.nu, view = w / it.nu;
     const long col = (long)view * it.nu + i;
     column_profiles<true>(it.proj + (long)view * it.nv * it.nu + i, it.nu, it.cols[col], it.zix[col], it.nv, it.nz,
@@ -479,8 +480,10 @@ __global__ void __launch_bounds__(256) k_adj_gather_staged_b(BGa B) {
     __shared__ GatherLds<32, GS_ROWS32> lds;
     const int r = batch_item(B.wg0, B.n);
     const BGaItem &it = B.it[r];
-    const int w = (int)blockIdx.x - B.wg0[r];
-    const int nzt = it.A.nz / 32, tzg = w / (it.ntx * it.nty), t2 = w - tzg * it.ntx * it.nty;
+    const int nzt = it.A.nz / 32;
+    const int w = cbct_batch_local(B.wg0[r], B.wg0[r + 1] - B.wg0[r]);
+    if (w >= it.ntx * it.nty * nzt * it.vgroups) return;  // padding
+    const int tzg = w / (it.ntx * it.nty), t2 = w - tzg * it.ntx * it.nty;
     gather_staged_body<32, GS_ROWS32>(lds, it.Z, it.zix, it.cols, it.views, it.A, t2 % it.ntx, t2 / it.ntx, tzg % nzt,
                                       tzg / nzt, it.vgroups, it.vper, it.fbase, it.kappa, it.out, it.out2, it.part);
 }
@@ -624,16 +627,16 @@ cbct_status cbct_launch_adjoint_batch(const AdjReq *r, int n, hipStream_t s, int
             const bool gb = l1 <= 64 * 1024;
             if (!gb) l1 = sizeof(double2) * (L.nv + 1);
             lds = std::max(lds, l1);
-            P.it[j] = BPrItem{a.proj, L.d_cols, L.d_zix, a.Zws, L.nu, L.nv, L.nz, gb ? 1 : 0, (float)L.pv};
+            P.it[j] = BPrItem{a.proj, L.d_cols, L.d_zix, a.Zws, L.nu, L.nv, L.nz, L.nviews, gb ? 1 : 0, (float)L.pv};
             P.wg0[j] = wp;
-            wp += L.nu * L.nviews;
+            wp += cbct_batch_pad(L.nu * L.nviews);
             const int vg = L.adj_vsplit, vper = (L.nviews + vg - 1) / vg;
             const int ntx = (L.nx + ADJ_TX - 1) / ADJ_TX, nty = (L.ny + ADJ_TY - 1) / ADJ_TY;
             float *part = a.Zws + L.adj_part_off;
             G.it[j] = BGaItem{a.Zws, L.d_zix, L.d_cols, L.d_views, a.fbase, a.out, a.out2, part, L.adj,
                               ntx, nty, vg, vper, a.kappa};
             G.wg0[j] = wg;
-            wg += ntx * nty * (L.nz / 32) * vg;
+            wg += cbct_batch_pad(ntx * nty * (L.nz / 32) * vg);
             if (vg > 1) {
                 const long nvox = L.nvox();
                 C.it[C.n] = BCoItem{part, a.fbase, a.out, a.out2, nvox, vg, a.kappa};

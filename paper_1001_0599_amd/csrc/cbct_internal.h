@@ -118,6 +118,13 @@ __device__ __forceinline__ int cbct_xcd_remap(int w, int G) {
     return (G & 7) ? w : (w & 7) * (G >> 3) + (w >> 3);
 }
 
+// In a batched launch a request's work-groups start at wg0 and number G, both multiples of 8 (the
+// launcher pads G): the request's own index of this work-group in the XCD-aware order of a solo
+// launch of G work-groups (the XCD is blockIdx.x % 8, and wg0 % 8 == 0).  Indices past the
+// request's real count belong to padding work-groups, which return at once.
+__device__ __forceinline__ int cbct_batch_local(int wg0, int G) { return cbct_xcd_remap((int)blockIdx.x - wg0, G); }
+inline int cbct_batch_pad(int n) { return (n + 7) & ~7; }
+
 // Device-side result of one Armijo search window (read by the host after each ROF iteration).
 struct RofControl {
     double e0;       // E_R(u)

@@ -452,7 +452,7 @@ struct BFwItem {
     const float *ysub;
     float *out;
     double *partials;
-    int nx, ny, nz, nu, nv;
+    int nx, ny, nz, nu, nv, nviews;
     float pv;
 };
 struct BFw {
@@ -466,7 +466,8 @@ __global__ void __launch_bounds__(256) k_forward_runs_b(BFw B) {
     int r = 0;
     while (r + 1 < B.n && (int)blockIdx.x >= B.wg0[r + 1]) r++;
     const BFwItem &it = B.it[r];
-    const int w = blockIdx.x - B.wg0[r];
+    const int w = cbct_batch_local(B.wg0[r], B.wg0[r + 1] - B.wg0[r]);
+    if (w >= it.nu * it.nviews) return;  // padding
     forward_runs_body<KC, NPT>(it.vol_t, it.cols, it.nx, it.ny, it.nz, it.nu, it.nv, it.pv, it.ysub, 1, it.out,
                                it.partials, w % it.nu, w / it.nu);
 }
@@ -611,9 +612,9 @@ cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s) {
             done[q2] = true;
             const Level &L = *r[q2].L;
             B.it[B.n] = BFwItem{r[q2].vol_t, L.d_cols, r[q2].ysub, r[q2].out, r[q2].partials, L.nx, L.ny, L.nz,
-                                L.nu, L.nv, (float)L.pv};
+                                L.nu, L.nv, L.nviews, (float)L.pv};
             B.wg0[B.n] = w;
-            w += L.nu * L.nviews;
+            w += cbct_batch_pad(L.nu * L.nviews);
             B.n++;
             size_t l2 = 0;
             switch (kc) {
