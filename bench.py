@@ -211,7 +211,8 @@ def small_solves():
     """Solves that are bound by launches and the ROF loop's decisions rather than by bandwidth:
     the 32^3 / 16-view cube (20 iterations), the low-dose 32^3 sweep (3 levels x 100 iterations,
     lambda 0.02 / 0.05 / 0.1, I0 = 2e3) and a 128^3 / 60-view volume (20 iterations, its ROF loop
-    on gated launch chains); milliseconds per solve, medians of repeated solves."""
+    on gated launch chains); and the autograd loss of the 8 x 128^3 batch with its backward pass.
+    Milliseconds per solve (or loss and backward), medians of repeats."""
     import numpy as np
     import torch
 
@@ -244,6 +245,28 @@ def small_solves():
     res["lowdose32_3x100it_ms"] = {str(lam): timed(plan, y, lam, c["iters"], 3) for lam in c["lam"]}
     g = S.CONFIGS["batch8x128"]["geometry"]
     res["vol128_60views_20it_ms"] = timed(Plan(g, levels=1), noisy(g, (41, 49), 1e5), 0.05, [20], 5)
+    # the autograd loss of the 8 x 128^3 batch: sum (P f - y)^2 + lambda TV(f), forward and backward
+    from paper_1001_0599_amd.autograd import project, tv_sum
+    c = S.CONFIGS["batch8x128"]
+    plan = Plan(g, levels=1)
+    torch.manual_seed(0)
+    f = (0.02 * torch.rand((c["batch"],) + tuple(g.vol_shape), device="cuda")).requires_grad_(True)
+    y = torch.rand((c["batch"],) + tuple(g.proj_shape), device="cuda")
+
+    def step():
+        f.grad = None
+        r = project(f, plan) - y
+        ((r * r).sum() + c["lam"] * tv_sum(f, plan)).backward()
+
+    step()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    res["autograd_8x128_loss_backward_ms"] = float(np.median(ts)) * 1e3
     return res
 
 
