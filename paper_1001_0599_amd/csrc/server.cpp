@@ -114,7 +114,7 @@ struct Request {
     // Step 2 of the current outer iteration: a gated loop ran (Step 3 applies its pending step);
     // the sequence numbers of the steps enqueued for it
     bool pending = false;
-    bool fresh = false;  // this round's loop is its first device-side Step 2
+    bool fresh = false;  // this outer iteration's loop is its first device-side Step 2
     std::vector<int> seqs;
 };
 
