@@ -1,7 +1,8 @@
 """Parity of the HIP Siddon projector pair (exact ray-in-voxel lengths) with the FP64 oracle.
 
-Bar: relative L2 <= 1e-4 (FP32 crossing parameters vs FP64 sorted crossings); at full size on
-sampled rays and voxels that the oracle computes one by one, plus the adjoint identity."""
+Bar: relative L2 <= 2e-5 (float lengths and sums against the FP64 sorted crossings; measured
+1e-7 to 7e-6); at full size on sampled rays and voxels that the oracle computes one by one, plus
+the adjoint identity."""
 import dataclasses
 
 import numpy as np
@@ -14,7 +15,7 @@ from tests.gpu_util import announce, rel_l2, to_gpu, to_np
 from tests.test_gpu_ops import CASES
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-4
+TOL = 2e-5
 
 
 def _plan(g, levels=1):
