@@ -499,6 +499,116 @@ def trace_summary(d, top=40):
     print("all kernels: %.3f ms" % (tot / 1e6))
 
 
+def occupancy_run(which):
+    """A workload for a GPU-busy record under a rocprofv3 kernel trace: warm-up passes (plans,
+    cached Schur steps and workspaces in place), a 0.5 s pause that marks the window, then timed
+    passes back to back.  'recon': three 512x512x64 / 40-view reconstructions; 'cube32': five
+    32^3 / 16-view solves; 'plain32': the plain one-at-a-time loop over the first 32 requests of
+    the serving workload (one plan per geometry, each warmed once)."""
+    import torch
+
+    import cbct_synth as S
+    from paper_1001_0599_amd.ops import Plan
+
+    def noisy(g, seeds, i0):
+        ph = S.make_phantom(g, seeds[0])
+        return S.poisson_log_torch(S.analytic_projections_torch(g, ph, "cuda"), i0, seeds[1]).float().contiguous()
+
+    jobs = []  # (plan, y, lam, iters, out)
+    if which in ("recon", "cube32"):
+        c = S.CONFIGS["wide512x512x64" if which == "recon" else "cube32"]
+        g = c["geometry"]
+        plan = Plan(g, levels=c["levels"])
+        y = noisy(g, c["seeds"], c["I0"])
+        out = torch.empty(plan.vol_shape(0), device="cuda")
+        jobs = [(plan, y, c["lam"], tuple(c["iters"]), out)] * (3 if which == "recon" else 5)
+        warm = jobs[:1]
+    elif which == "plain32":
+        cfg = S.CONFIGS["serving_mix"]
+        plans, warm = {}, []
+        for r in S.serving_requests(32):
+            g = r["geometry"]
+            key = (g.nx, g.ny, g.nz, g.n_views, g.nu, g.nv)
+            y = noisy(g, (r["phantom_seed"], r["noise_seed"]), cfg["I0"])
+            fresh = key not in plans
+            if fresh:
+                plans[key] = Plan(g)
+            job = (plans[key], y, cfg["lam"], tuple(cfg["iters"]), torch.empty(g.vol_shape, device="cuda"))
+            if fresh:
+                warm.append(job)
+            jobs.append(job)
+    else:
+        raise SystemExit("unknown occupancy workload %r (recon, cube32, plain32)" % which)
+    for plan, y, lam, iters, out in warm:
+        plan.reconstruct(y, lam=lam, iters=iters, out=out)
+    torch.cuda.synchronize()
+    time.sleep(0.5)
+    t0 = time.perf_counter()
+    for plan, y, lam, iters, out in jobs:
+        plan.reconstruct(y, lam=lam, iters=iters, out=out)
+    torch.cuda.synchronize()
+    print("%s: %d passes in %.2f ms (wall)" % (which, len(jobs), (time.perf_counter() - t0) * 1e3), flush=True)
+
+
+def busy_summary(d, passes, top=16):
+    """GPU-busy record of an occupancy run's kernel trace: the window is everything after the
+    trace's longest gap between kernels (the run's pause); busy time is the union of the kernels'
+    intervals in it, against the window from the first kernel's start to the last one's end."""
+    import glob
+    import re
+    import sqlite3
+    from collections import defaultdict
+
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit("no rocprofv3 database under %s" % d)
+    con = sqlite3.connect(dbs[0])
+    cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
+    wgc = [next((c for c in cols if re.fullmatch(r"(workgroup|wg)(_size)?_%s" % ax, c)), None) for ax in "xyz"]
+    sel = "name, start, end, grid_x, grid_y, grid_z" + ("".join(", " + c for c in wgc) if all(wgc) else "")
+    rows = list(con.execute("select %s from kernels order by start" % sel))
+    if len(rows) < 2:
+        raise SystemExit("too few kernels in the trace")
+    gi = max(range(len(rows) - 1), key=lambda i: rows[i + 1][1] - rows[i][2])
+    win = rows[gi + 1:]
+    t0, t1 = win[0][1], max(r[2] for r in win)
+    busy, cs, ce = 0, None, None
+    for _, st, en, *_ in win:
+        if ce is None or st > ce:
+            if ce is not None:
+                busy += ce - cs
+            cs, ce = st, en
+        else:
+            ce = max(ce, en)
+    busy += ce - cs
+    ksum = sum(en - st for _, st, en, *_ in win)
+    print("window %.3f ms (first kernel start to last kernel end), GPU busy %.3f ms = %.1f %%" % (
+        (t1 - t0) / 1e6, busy / 1e6, 100.0 * busy / (t1 - t0)))
+    print("kernels %d (%.1f per pass over %d passes), summed durations %.3f ms, mean %.2f us" % (
+        len(win), len(win) / passes, passes, ksum / 1e6, ksum / len(win) / 1e3))
+    if all(wgc):
+        # launches by work-group count: 256 CUs hold at least 2 work-groups of 256 lanes each
+        bins = [(0, 256), (256, 1024), (1024, 4096), (4096, 1 << 62)]
+        tb = [0] * len(bins)
+        for _, st, en, gx, gy, gz, wx, wy, wz in win:
+            nwg = -(-gx // max(wx, 1)) * -(-gy // max(wy, 1)) * -(-gz // max(wz, 1))
+            tb[next(i for i, (lo, hi) in enumerate(bins) if lo <= nwg < hi)] += en - st
+        print("kernel time by launch size: " + ", ".join(
+            "%s work-groups %.1f %%" % ("%d-%d" % (lo, hi - 1) if hi < 1 << 62 else ">= %d" % lo, 100.0 * t / ksum)
+            for (lo, hi), t in zip(bins, tb)))
+    else:
+        print("(no work-group size columns in the trace's kernel table: %s)" % ", ".join(cols))
+    agg = defaultdict(lambda: [0, 0])
+    for n, st, en, *_ in win:
+        k = re.sub(r"^void ", "", n).replace("(anonymous namespace)::", "")
+        k = re.sub(r"\(.*", "", k)
+        agg[k][0] += en - st
+        agg[k][1] += 1
+    print("%-46s %7s %10s %9s" % ("kernel", "calls", "total ms", "mean us"))
+    for k, (du, c) in sorted(agg.items(), key=lambda kv: -kv[1][0])[:top]:
+        print("%-46s %7d %10.3f %9.2f" % (k[:46], c, du / 1e6, du / c / 1e3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -512,7 +622,17 @@ def main():
                     help="print the traffic / L2 hit-rate record from three counter runs of --kernels-only")
     ap.add_argument("--trace-summary", metavar="DIR", help="per-kernel table of a rocprofv3 kernel-trace run")
     ap.add_argument("--sq-summary", metavar="DIR", help="instruction-mix record from a rocprofv3 SQ-counter run")
+    ap.add_argument("--occupancy", choices=("recon", "cube32", "plain32"),
+                    help="run one workload for a GPU-busy kernel trace (see --busy-summary)")
+    ap.add_argument("--busy-summary", nargs=2, metavar=("DIR", "PASSES"),
+                    help="GPU-busy record of a rocprofv3 kernel trace of an --occupancy run")
     args = ap.parse_args()
+    if args.occupancy:
+        occupancy_run(args.occupancy)
+        return
+    if args.busy_summary:
+        busy_summary(args.busy_summary[0], int(args.busy_summary[1]))
+        return
     if args.counter_summary:
         counter_summary(*args.counter_summary)
         return
