@@ -207,6 +207,62 @@ def serving_run(n_requests):
     return res
 
 
+def operator_table():
+    """P (cbct_forward, with its copy of the volume into z-contiguous columns) and P^T
+    (cbct_adjoint) at each configuration and level: the 32^3 / 16-view cube, both levels of the
+    512x512x64 / 40-view benchmark and the 8 x 128^3 / 60-view batch (one call per volume), on
+    seeded uniform volumes and projections.  HIP events on the stream they run on, 3 warm-ups,
+    then the median and 90th percentile of 20 runs; voxel.views/s from the median."""
+    import numpy as np
+    import torch
+
+    import cbct_synth as S
+    from paper_1001_0599_amd.ops import Plan
+
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    cases = (("cube32", S.CONFIGS["cube32"], (0,), 1), ("wide512x512x64", S.CONFIGS["wide512x512x64"], (0, 1), 1),
+             ("batch8x128", S.CONFIGS["batch8x128"], (0,), S.CONFIGS["batch8x128"]["batch"]))
+    res = {}
+    for name, c, lvls, batch in cases:
+        g = c["geometry"]
+        plan = Plan(g, levels=c.get("levels", 1))
+        for lvl in lvls:
+            vs, ps = plan.vol_shape(lvl), plan.proj_shape(lvl)
+            f = torch.rand((batch,) + vs, device="cuda", generator=gen) * 0.02
+            y = torch.rand((batch,) + ps, device="cuda", generator=gen)
+            p, v = torch.empty_like(y), torch.empty_like(f)
+            fws = torch.empty(plan.forward_workspace_bytes(lvl), dtype=torch.uint8, device="cuda")
+            aws = torch.empty(plan.adjoint_workspace_bytes(lvl), dtype=torch.uint8, device="cuda")
+
+            def fwd():
+                for b in range(batch):
+                    plan.forward(f[b], level=lvl, out=p[b], workspace=fws)
+
+            def adj():
+                for b in range(batch):
+                    plan.adjoint(y[b], level=lvl, out=v[b], workspace=aws)
+
+            row = {"volume": "x".join(str(n) for n in vs[::-1]) + ("" if batch == 1 else " x %d" % batch),
+                   "views": ps[0], "detector": "%dx%d" % (ps[2], ps[1])}
+            vv = batch * vs[0] * vs[1] * vs[2] * ps[0]
+            for op, fn in (("P", fwd), ("P^T", adj)):
+                for _ in range(3):
+                    fn()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+                for e0, e1 in ev:
+                    e0.record()
+                    fn()
+                    e1.record()
+                torch.cuda.synchronize()
+                ms = np.array([a.elapsed_time(b) for a, b in ev])
+                med, p90 = float(np.median(ms)), float(np.percentile(ms, 90))
+                row[op] = {"median_ms": med, "p90_ms": p90, "voxel_views_per_s": vv / (med * 1e-3)}
+            res["%s level %d" % (name, lvl)] = row
+            del f, y, p, v, fws, aws
+    return res
+
+
 def small_solves():
     """Solves that are bound by launches and the ROF loop's decisions rather than by bandwidth:
     the 32^3 / 16-view cube (20 iterations), the low-dose 32^3 sweep (3 levels x 100 iterations,
@@ -799,6 +855,8 @@ def main():
     }
     log("launch-bound solves: 32^3, low-dose 32^3 sweep, 128^3")
     res["solves"] = small_solves()
+    log("per-operator table: cbct_forward / cbct_adjoint per configuration and level")
+    res["operators"] = operator_table()
     if args.serving:
         res["serving"] = serving_run(args.serving)
     if not args.no_cpu_baseline:
