@@ -59,6 +59,20 @@ def measured_traffic():
         return None, None
 
 
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo) and the logical CPUs the OS reports."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(g, iters, lam):
     """The FP64 oracle on the host cores, on bounded samples of the workload:
     - all threads: P and P^T of 12 of the 40 views (every ray of those views, the full volume),
@@ -861,7 +875,14 @@ def main():
         res["serving"] = serving_run(args.serving)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample)")
-        res["cpu_baseline"] = cpu_baseline(g, iters, lam)
+        cb = cpu_baseline(g, iters, lam)
+        cb["host"] = host_cpu()
+        # the same rate on the GPU (P and P^T at the fine level) and the same job, over the oracle's
+        gpu_pair = 2.0 * vv / (tp + ta)
+        cb["gpu_over_oracle"] = gpu_pair / cb["value"]
+        cb["gpu_over_oracle_1thread"] = gpu_pair / cb["value_1thread"]
+        cb["recon_gpu_over_oracle_extrapolated"] = cb["recon_s_extrapolated"] / recon_s
+        res["cpu_baseline"] = cb
     print(json.dumps(res), flush=True)
 
 
