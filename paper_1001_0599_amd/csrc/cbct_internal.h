@@ -79,8 +79,12 @@ cbct_status cbct_hip_error(hipError_t e, const char *what);
     } while (0)
 
 // kernel launchers (each checks its launch)
-// chunk of the run-summing projector for nz cells (0: its LDS tables do not fit)
-int cbct_forward_run_chunk(int nz);
+// work-group size of the run-summing projector for nv detector rows (row pairs split evenly over
+// threads, whole waves); *npt: row pairs per thread
+int cbct_forward_runs_block(int nv, int *npt);
+// chunk of the run-summing projector for nz cells and work-groups of nwaves waves (0: its LDS
+// tables do not fit)
+int cbct_forward_run_chunk(int nz, int nwaves);
 cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_t, hipStream_t s);
 // y_sub == NULL: out = P f.  Otherwise residual mode: out = w * (P f - y_sub) (the ray weight
 // applied, ready for the pre-weighted adjoint; plain P f - y_sub when weight_residual is false)

@@ -151,7 +151,7 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     L.fwd_tw = L.nz + 2 * L.fwd_pad + 3;
     L.fwd_kc = ((size_t)L.fwd_tw * 65 * 4 <= 56 * 1024) ? 32 : 16;
     // the run-summing projector (no z padding needed; 32-bit byte offsets into the volume)
-    L.fwd_kr = L.nvox() * 4 < (1L << 31) ? cbct_forward_run_chunk(L.nz) : 0;
+    L.fwd_kr = L.nvox() * 4 < (1L << 31) ? cbct_forward_run_chunk(L.nz, cbct_forward_runs_block(L.nv, nullptr) / 64) : 0;
     if (L.fwd_kr == 0 && (size_t)L.fwd_tw * (2 * L.fwd_kc + 1) * 4 > 60 * 1024)
         return cbct_set_error(CBCT_ERR_INVALID_ARG,
                               "level %d: cone too wide for the projector tables (%d z cells)", l, L.fwd_tw);
@@ -174,9 +174,10 @@ static cbct_status build_level(const cbct_geometry_desc *g, int l, int bin, Leve
     A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.nu = L.nu; A.nv = L.nv; A.nviews = L.nviews;
     A.hx = (float)L.hx; A.hy = (float)L.hy; A.hz = (float)L.hz; A.pu = (float)L.pu; A.pv = (float)L.pv;
     A.sad = (float)L.sad; A.sdd = (float)L.sdd;
-    // whole chunks for the projector: extend every sample range to a multiple of both chunk sizes
-    // (powers of two; the extra samples lie beyond the grid, where all interpolation weights vanish)
-    const int kpad = std::max(L.fwd_kc, L.fwd_kr);
+    // whole chunks for the projector: extend every sample range to a multiple of the chunk of the
+    // projector this level runs (the run-summing one when it fits, else the per-sample one; the
+    // extra samples lie beyond the grid, where all interpolation weights vanish)
+    const int kpad = L.fwd_kr > 0 ? L.fwd_kr : L.fwd_kc;
     for (auto &c : cols)
         if (c.khi >= c.klo) c.khi = c.klo + ((c.khi - c.klo + kpad) / kpad) * kpad - 1;
 

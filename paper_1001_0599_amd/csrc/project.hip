@@ -230,11 +230,14 @@ __device__ __forceinline__ float ldv(__amdgpu_buffer_rsrc_t r, int off, int, int
 // slices' totals, and every thread then sums its pair of rays run by run.  The table is cell-major,
 // [e][k] with k = 0 .. KC: column e holds voxel e - 1; cells 0 and nz + 1 stay zero, so rays
 // leaving the slab read zeros.
+__host__ __device__ constexpr size_t runs_lds_bytes_kc(int kc, int nz, int nwaves) {
+    // slice totals: one row of nz per builder (a wave, or half a wave for depths of 32 or less)
+    return ((size_t)(nz + 2) * (kc + 1) * 8 + 15) / 16 * 16 + (size_t)kc * 32 +
+           (size_t)(nz <= 32 ? 2 * nwaves : nwaves) * nz * 8;
+}
 template <int KC>
 __host__ __device__ constexpr size_t runs_lds_bytes(int nz, int nwaves) {
-    // slice totals: one row of nz per builder (a wave, or half a wave for depths of 32 or less)
-    return ((size_t)(nz + 2) * (KC + 1) * 8 + 15) / 16 * 16 + (size_t)KC * 32 +
-           (size_t)(nz <= 32 ? 2 * nwaves : nwaves) * nz * 8;
+    return runs_lds_bytes_kc(KC, nz, nwaves);
 }
 
 template <int KC, int NPT>
@@ -242,6 +245,7 @@ __device__ __forceinline__ void forward_runs_body(const float *__restrict__ vol_
                                                   int nx, int ny, int nz, int nu, int nv, float pv,
                                                   const float *__restrict__ ysub, int wres, float *__restrict__ out,
                                                   double *__restrict__ partials, int i, int view) {
+    static_assert(KC % 8 == 0 && KC >= 8 && KC <= 64, "chunks are whole groups of 8 samples, at most 64");
     extern __shared__ float4 lds4[];
     constexpr int S = KC + 1;  // entries per cell: (A, K) before local sample k = 0 .. KC
     const int tw = nz + 2;
@@ -525,20 +529,34 @@ cbct_status cbct_launch_to_columns(const Level &L, const float *vol, float *vol_
     return CBCT_OK;
 }
 
-// The largest chunk of at least 16 samples whose tables fit 32 KB of LDS, else the largest that
-// fits 48 KB (deep grids): the projector lives on occupancy more than on chunk length (at 128^3 /
-// 60 views 16-sample chunks, eight work-groups per CU, took 0.25 ms per P against 0.30 with
-// 32-sample chunks at four per CU and 0.56 with 64-sample ones at two; at 512x512x64 / 40 views
-// 32-sample chunks 0.80 against 0.82 ms with 64).
-int cbct_forward_run_chunk(int nz) {
-    constexpr size_t small = 32 * 1024, budget = 48 * 1024;
-    if (runs_lds_bytes<64>(nz, 4) <= small) return 64;
-    if (runs_lds_bytes<32>(nz, 4) <= small) return 32;
-    if (runs_lds_bytes<16>(nz, 4) <= small) return 16;
-    if (runs_lds_bytes<64>(nz, 4) <= budget) return 64;
-    if (runs_lds_bytes<32>(nz, 4) <= budget) return 32;
-    if (runs_lds_bytes<16>(nz, 4) <= budget) return 16;
-    if (runs_lds_bytes<8>(nz, 4) <= budget) return 8;
+int cbct_forward_runs_block(int nv, int *npt) {
+    const int npairs = (nv + 1) / 2;
+    int n = 1;
+    while ((npairs + n - 1) / n > 256) n *= 2;
+    if (npt) *npt = n;
+    return (((npairs + n - 1) / n + 63) / 64) * 64;
+}
+
+// The chunk (samples per table).  With two or more waves, which split each chunk's build into
+// slices of whole groups of 8 samples, the largest multiple of 8 from 64 down to 16 whose tables
+// leave LDS for six work-groups per CU (160 KB / 6); otherwise (one wave, or depths above 112 where
+// no such chunk fits) the largest of 64, 32 or 16 within 32 KB, else the largest of 64, 32, 16 or 8
+// within 48 KB.  The projector lives on occupancy and on the build's balance over the waves: at
+// 512x512x64 / 40 views (three waves) 40 samples, slices of 16, 16 and 8 at six work-groups per CU,
+// took 0.74-0.76 ms per P against 0.77-0.78 with 48 (balanced, five per CU), 0.79-0.81 with 32
+// (slices 16, 16 and none) and 0.84 with 24; at 256x256x96 / 82 views (two waves) 24 samples took
+// 1.13 against 1.32 ms with 32; a one-wave 64^3 took 0.054 ms with 32 against 0.060 with 40; at
+// 128^3 / 60 views 16-sample chunks, eight work-groups per CU, took 0.25 ms against 0.30 with 32 at
+// four per CU and 0.56 with 64 at two.
+int cbct_forward_run_chunk(int nz, int nwaves) {
+    constexpr size_t six = 160 * 1024 / 6, small = 32 * 1024, budget = 48 * 1024;
+    if (nwaves >= 2)
+        for (int kc = 64; kc >= 16; kc -= 8)
+            if (runs_lds_bytes_kc(kc, nz, 4) <= six) return kc;
+    for (int kc = 64; kc >= 16; kc /= 2)
+        if (runs_lds_bytes_kc(kc, nz, 4) <= small) return kc;
+    for (int kc = 64; kc >= 8; kc /= 2)
+        if (runs_lds_bytes_kc(kc, nz, 4) <= budget) return kc;
     return 0;
 }
 
@@ -547,15 +565,15 @@ cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float 
     const int wres = weight_residual ? 1 : 0;
     if (L.fwd_kr > 0) {
         // rays per thread and a work-group size that splits the rows evenly
-        const int npairs = (L.nv + 1) / 2;
         int npt = 1;
-        while ((npairs + npt - 1) / npt > 256) npt *= 2;
-        const int block = (((npairs + npt - 1) / npt + 63) / 64) * 64;
-        if (L.fwd_kr == 64) return dispatch_fwd_runs<64>(L, vol_t, ysub, wres, out, partials, s, npt, block);
-        if (L.fwd_kr == 32) return dispatch_fwd_runs<32>(L, vol_t, ysub, wres, out, partials, s, npt, block);
-        if (L.fwd_kr == 16) return dispatch_fwd_runs<16>(L, vol_t, ysub, wres, out, partials, s, npt, block);
-        if (L.fwd_kr == 8) return dispatch_fwd_runs<8>(L, vol_t, ysub, wres, out, partials, s, npt, block);
-        return cbct_set_error(CBCT_ERR_INVALID_ARG, "forward: %d detector rows is more than supported", L.nv);
+        const int block = cbct_forward_runs_block(L.nv, &npt);
+        switch (L.fwd_kr) {
+#define CBCT_FWR(KC_) \
+    case KC_: return dispatch_fwd_runs<KC_>(L, vol_t, ysub, wres, out, partials, s, npt, block);
+            CBCT_FWR(64) CBCT_FWR(56) CBCT_FWR(48) CBCT_FWR(40) CBCT_FWR(32) CBCT_FWR(24) CBCT_FWR(16) CBCT_FWR(8)
+#undef CBCT_FWR
+            default: return cbct_set_error(CBCT_ERR_INTERNAL, "forward: unsupported chunk %d", L.fwd_kr);
+        }
     }
     const int npairs = (L.nv + 1) / 2;
     int block = ((npairs + 63) / 64) * 64;
@@ -588,10 +606,7 @@ cbct_status cbct_launch_forward(const Level &L, const float *vol_t, const float 
 // the run-summing projector's configuration of a level: chunk, row pairs per thread, block size
 static bool fwd_runs_config(const Level &L, int &kc, int &npt, int &block) {
     if (L.fwd_kr <= 0) return false;
-    const int npairs = (L.nv + 1) / 2;
-    npt = 1;
-    while ((npairs + npt - 1) / npt > 256) npt *= 2;
-    block = (((npairs + npt - 1) / npt + 63) / 64) * 64;
+    block = cbct_forward_runs_block(L.nv, &npt);
     kc = L.fwd_kr;
     return npt <= 8;
 }
@@ -624,14 +639,7 @@ cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s) {
             B.wg0[B.n] = w;
             w += cbct_batch_pad(L.nu * L.nviews);
             B.n++;
-            size_t l2 = 0;
-            switch (kc) {
-                case 64: l2 = runs_lds_bytes<64>(L.nz, block / 64); break;
-                case 32: l2 = runs_lds_bytes<32>(L.nz, block / 64); break;
-                case 16: l2 = runs_lds_bytes<16>(L.nz, block / 64); break;
-                default: l2 = runs_lds_bytes<8>(L.nz, block / 64); break;
-            }
-            lds = std::max(lds, l2);
+            lds = std::max(lds, runs_lds_bytes_kc(kc, L.nz, block / 64));
         }
         B.wg0[B.n] = w;
         cbct_status st = CBCT_OK;
@@ -640,10 +648,17 @@ cbct_status cbct_launch_forward_batch(const FwdReq *r, int n, hipStream_t s) {
     else if (npt == 2) st = launch_fwd_runs_b<KC_, 2>(B, lds, block, s);        \
     else if (npt == 4) st = launch_fwd_runs_b<KC_, 4>(B, lds, block, s);        \
     else st = launch_fwd_runs_b<KC_, 8>(B, lds, block, s);
-        if (kc == 64) { CBCT_FWB(64) }
-        else if (kc == 32) { CBCT_FWB(32) }
-        else if (kc == 16) { CBCT_FWB(16) }
-        else { CBCT_FWB(8) }
+        switch (kc) {
+            case 64: CBCT_FWB(64) break;
+            case 56: CBCT_FWB(56) break;
+            case 48: CBCT_FWB(48) break;
+            case 40: CBCT_FWB(40) break;
+            case 32: CBCT_FWB(32) break;
+            case 24: CBCT_FWB(24) break;
+            case 16: CBCT_FWB(16) break;
+            case 8: CBCT_FWB(8) break;
+            default: st = cbct_set_error(CBCT_ERR_INTERNAL, "forward: unsupported chunk %d", kc);
+        }
 #undef CBCT_FWB
         if (st) return st;
     }
