@@ -537,22 +537,27 @@ int cbct_forward_runs_block(int nv, int *npt) {
     return (((npairs + n - 1) / n + 63) / 64) * 64;
 }
 
-// The chunk (samples per table).  With two or more waves, which split each chunk's build into
-// slices of whole groups of 8 samples, the largest multiple of 8 from 64 down to 16 whose tables
-// leave LDS for six work-groups per CU (160 KB / 6); otherwise (one wave, or depths above 112 where
-// no such chunk fits) the largest of 64, 32 or 16 within 32 KB, else the largest of 64, 32, 16 or 8
-// within 48 KB.  The projector lives on occupancy and on the build's balance over the waves: at
-// 512x512x64 / 40 views (three waves) 40 samples, slices of 16, 16 and 8 at six work-groups per CU,
-// took 0.74-0.76 ms per P against 0.77-0.78 with 48 (balanced, five per CU), 0.79-0.81 with 32
-// (slices 16, 16 and none) and 0.84 with 24; at 256x256x96 / 82 views (two waves) 24 samples took
-// 1.13 against 1.32 ms with 32; a one-wave 64^3 took 0.054 ms with 32 against 0.060 with 40; at
-// 128^3 / 60 views 16-sample chunks, eight work-groups per CU, took 0.25 ms against 0.30 with 32 at
-// four per CU and 0.56 with 64 at two.
+// The chunk (samples per table).  One-wave work-groups (up to 128 detector rows) take 16 samples
+// (8 where those tables do not fit 48 KB): with no build to split, the most work-groups per CU win.
+// With two or more waves, which split each chunk's build into slices of whole groups of 8 samples,
+// the largest multiple of 8 from 64 down to 16 whose tables leave LDS for six work-groups per CU
+// (160 KB / 6); where none does (depths above 112), the largest of 64, 32 or 16 within 32 KB, else
+// the largest of 64, 32, 16 or 8 within 48 KB.  The projector lives on occupancy and on the
+// build's balance over the waves: at 512x512x64 / 40 views (three waves) 40 samples, slices of 16,
+// 16 and 8 at six work-groups per CU, took 0.74-0.76 ms per P against 0.77-0.78 with 48 (balanced,
+// five per CU), 0.79-0.81 with 32 (slices 16, 16 and none) and 0.84 with 24; at 256x256x96 / 82
+// views (two waves) 24 samples took 1.13 against 1.32 ms with 32; one-wave 64^3 / 77 views took
+// 0.043 ms with 16 against 0.046 with 24 and 0.054 with 32, and 32^3 / 16 views 0.010 against
+// 0.012 ms with 64; at 128^3 / 60 views 16-sample chunks, eight work-groups per CU, took 0.25 ms
+// against 0.30 with 32 at four per CU and 0.56 with 64 at two.
 int cbct_forward_run_chunk(int nz, int nwaves) {
     constexpr size_t six = 160 * 1024 / 6, small = 32 * 1024, budget = 48 * 1024;
-    if (nwaves >= 2)
-        for (int kc = 64; kc >= 16; kc -= 8)
-            if (runs_lds_bytes_kc(kc, nz, 4) <= six) return kc;
+    if (nwaves == 1) {
+        if (runs_lds_bytes_kc(16, nz, 4) <= budget) return 16;
+        return runs_lds_bytes_kc(8, nz, 4) <= budget ? 8 : 0;
+    }
+    for (int kc = 64; kc >= 16; kc -= 8)
+        if (runs_lds_bytes_kc(kc, nz, 4) <= six) return kc;
     for (int kc = 64; kc >= 16; kc /= 2)
         if (runs_lds_bytes_kc(kc, nz, 4) <= small) return kc;
     for (int kc = 64; kc >= 8; kc /= 2)
