@@ -776,6 +776,27 @@ cbct_status cbct_launch_forward_siddon(const Level &L, const float *vol_t, const
         const int kmax = L.nx + L.ny + 3;
         constexpr size_t budget = 48 * 1024;
         const bool fits32 = ((long)L.nx * L.ny * L.nz + (long)L.nz) * 4 < (1L << 31);  // 32-bit byte offsets
+        // With two or more waves, which split each chunk's table build into slices of whole groups
+        // of 8 pieces, the largest chunk of equal slices (a multiple of 8 x waves, at most 64) whose
+        // tables fit 32 KB (five work-groups per CU): at 512x512x64 / 40 views (three waves) 24
+        // pieces took 1.06 ms per P_s against 1.10 with 40, 1.16 with 16 and 1.27 with 32 (slices
+        // 16, 16 and none, four work-groups per CU).  Otherwise the largest of 64, 32 or 16 within
+        // 48 KB.
+        const int nw = block / 64, step = 8 * nw;
+        if (fits32 && npt <= 8 && nw >= 2) {
+            for (int kp = 64 / step * step; kp >= step; kp -= step) {
+                const size_t l = sid_runs_lds(kp, L.nz, kmax, nw);
+                if (l > 32 * 1024) continue;
+                switch (kp) {
+                    case 64: return launch_sid_runs<64>(L, vol_t, ysub, out, partials, s, npt, block, kmax, l);
+                    case 48: return launch_sid_runs<48>(L, vol_t, ysub, out, partials, s, npt, block, kmax, l);
+                    case 32: return launch_sid_runs<32>(L, vol_t, ysub, out, partials, s, npt, block, kmax, l);
+                    case 24: return launch_sid_runs<24>(L, vol_t, ysub, out, partials, s, npt, block, kmax, l);
+                    case 16: return launch_sid_runs<16>(L, vol_t, ysub, out, partials, s, npt, block, kmax, l);
+                    default: break;
+                }
+            }
+        }
         if (fits32 && npt <= 8 && sid_runs_lds(64, L.nz, kmax, block / 64) <= budget)
             return launch_sid_runs<64>(L, vol_t, ysub, out, partials, s, npt, block, kmax,
                                          sid_runs_lds(64, L.nz, kmax, block / 64));
