@@ -541,7 +541,7 @@ int cbct_forward_runs_block(int nv, int *npt) {
 // (8 where those tables do not fit 48 KB): with no build to split, the most work-groups per CU win.
 // With two or more waves, which split each chunk's build into slices of whole groups of 8 samples,
 // the largest multiple of 8 from 64 down to 16 whose tables leave LDS for six work-groups per CU
-// (160 KB / 6); where none does (depths above 112), the largest of 64, 32 or 16 within 32 KB, else
+// (160 KB / 6); where none does (depths above 157), the largest of 64, 32 or 16 within 32 KB, else
 // the largest of 64, 32, 16 or 8 within 48 KB.  The projector lives on occupancy and on the
 // build's balance over the waves: at 512x512x64 / 40 views (three waves) 40 samples, slices of 16,
 // 16 and 8 at six work-groups per CU, took 0.74-0.76 ms per P against 0.77-0.78 with 48 (balanced,
